@@ -1,0 +1,181 @@
+"""Plain FP64 CPU oracle for the shift-and-stack search (test infrastructure).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library and its Python binding
+never import it; the two share no code, only the seeded input arrays from
+``synth``.
+
+The arithmetic lives in ``kbm_oracle.c`` (plain C loops transcribing the
+definitions; see that file's header for the passages each function
+follows).  This module builds it with gcc and marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kbm_oracle.c")
+_LIB = os.path.join(_HERE, "libkbm_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+GCC_FLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+             "-fno-fast-math", "-std=c99"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP contraction off, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *GCC_FLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if (not os.path.exists(_LIB)
+                or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+        lib.kbmo_planes.argtypes = [i32, i32, i32, P, P, P, P, i32, P, P]
+        lib.kbmo_offsets.argtypes = [i32, P, i32, P, P]
+        lib.kbmo_offsets.restype = None
+        lib.kbmo_sigmag.argtypes = [i64, i32, P, P, P, f64, f64, f64, f64, P, P]
+        lib.kbmo_search.argtypes = [i32, i32, i32, P, P, P, i32, P, i32, i32,
+                                    i32, f64, f64, f64, f64, i32, i32, i32,
+                                    i32, P, P, P, P, P, P]
+        lib.kbmo_refine.argtypes = [i32, i32, i32, P, P, P, i64, P, P, P, P,
+                                    P, P, P]
+        lib.kbmo_num_threads.restype = C.c_int
+        _lib = lib
+        return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return None if a is None else np.ascontiguousarray(a, dtype=dt)
+
+
+def num_threads() -> int:
+    return int(_load().kbmo_num_threads())
+
+
+def planes(sci, var, mask, psf):
+    """FP64 psi/phi planes ``[T][H][W]`` (PSF correlation, masked = weight 0)."""
+    lib = _load()
+    sci, var = _c(sci, np.float32), _c(var, np.float32)
+    mask = _c(mask, np.uint8)
+    psf = _c(psf, np.float32)
+    T, H, W = sci.shape
+    k = psf.shape[0]
+    psi = np.empty((T, H, W), np.float64)
+    phi = np.empty((T, H, W), np.float64)
+    rc = lib.kbmo_planes(T, H, W, _p(sci), _p(var), _p(mask), _p(psf), k,
+                         _p(psi), _p(phi))
+    if rc:
+        raise ValueError("oracle planes: bad arguments")
+    return psi, phi
+
+
+def offsets(times, vels):
+    """int32 ``[V][T][2]`` offsets floor(v*t + 1/2), t from the earliest epoch."""
+    lib = _load()
+    times = _c(times, np.float64)
+    vels = _c(vels, np.float32).reshape(-1, 2)
+    T, V = times.shape[0], vels.shape[0]
+    off = np.empty((V, T, 2), np.int32)
+    lib.kbmo_offsets(T, _p(times), V, _p(vels), _p(off))
+    return off
+
+
+def sigmag(psi_curve, phi_curve=None, valid=None, q_lo=0.25, q_hi=0.75,
+           coeff=0.7413, n_sigma=2.0):
+    """Standalone sigma_G filter over ``[n][T]`` lightcurves.
+
+    Returns (keep uint64 [n], lh float64 [n])."""
+    lib = _load()
+    ps = _c(psi_curve, np.float32)
+    n, T = ps.shape
+    ph = _c(phi_curve, np.float32)
+    va = _c(valid, np.uint8)
+    keep = np.empty(n, np.uint64)
+    lh = np.empty(n, np.float64)
+    rc = lib.kbmo_sigmag(n, T, _p(ps), _p(ph), _p(va), q_lo, q_hi, coeff,
+                         n_sigma, _p(keep), _p(lh))
+    if rc:
+        raise ValueError("oracle sigmag: bad arguments")
+    return keep, lh
+
+
+def search(psi, phi, times, vels, *, k=8, min_obs=1, sigmag=1, q_lo=0.25,
+           q_hi=0.75, coeff=0.7413, n_sigma=2.0, region=None, **_ignored):
+    """Exhaustive search over float32 planes.
+
+    ``region = (x_begin, y_begin, x_end, y_end)`` (default: whole image).
+    Returns a dict of ``[Hr][Wr][k]`` arrays: lh (filtered likelihood),
+    flux, vel_idx, n_obs, keep, lh_raw."""
+    lib = _load()
+    psi, phi = _c(psi, np.float32), _c(phi, np.float32)
+    times = _c(times, np.float64)
+    vels = _c(vels, np.float32).reshape(-1, 2)
+    T, H, W = psi.shape
+    if region is None:
+        region = (0, 0, W, H)
+    x0, y0, x1, y1 = (int(v) for v in region)
+    Hr, Wr = y1 - y0, x1 - x0
+    out = dict(lh=np.empty((Hr, Wr, k), np.float64),
+               flux=np.empty((Hr, Wr, k), np.float64),
+               vel_idx=np.empty((Hr, Wr, k), np.int32),
+               n_obs=np.empty((Hr, Wr, k), np.int32),
+               keep=np.empty((Hr, Wr, k), np.uint64),
+               lh_raw=np.empty((Hr, Wr, k), np.float64))
+    rc = lib.kbmo_search(T, H, W, _p(psi), _p(phi), _p(times), vels.shape[0],
+                         _p(vels), k, min_obs, int(sigmag), q_lo, q_hi, coeff,
+                         n_sigma, x0, y0, x1, y1, _p(out["lh"]),
+                         _p(out["flux"]), _p(out["vel_idx"]), _p(out["n_obs"]),
+                         _p(out["keep"]), _p(out["lh_raw"]))
+    if rc:
+        raise ValueError("oracle search: bad arguments (rc=%d)" % rc)
+    return out
+
+
+def refine(psi, phi, times, params, keep=None, grad_lh=None, want_planes=False):
+    """Bilinear refinement objective L for ``[n][4]`` params (x0, y0, vx, vy).
+
+    With ``grad_lh`` given, also returns g * dL/dparams and, if
+    ``want_planes``, the accumulated dL/dpsi and dL/dphi planes."""
+    lib = _load()
+    psi, phi = _c(psi, np.float32), _c(phi, np.float32)
+    times = _c(times, np.float64)
+    params = _c(params, np.float32).reshape(-1, 4)
+    T, H, W = psi.shape
+    n = params.shape[0]
+    keep = _c(keep, np.uint64)
+    g = _c(grad_lh, np.float64)
+    lh = np.empty(n, np.float64)
+    gp = np.zeros((n, 4), np.float64) if g is not None else None
+    gpsi = np.zeros((T, H, W), np.float64) if (g is not None and want_planes) else None
+    gphi = np.zeros((T, H, W), np.float64) if (g is not None and want_planes) else None
+    rc = lib.kbmo_refine(T, H, W, _p(psi), _p(phi), _p(times), n, _p(params),
+                         _p(keep), _p(g), _p(lh), _p(gp), _p(gpsi), _p(gphi))
+    if rc:
+        raise ValueError("oracle refine: bad arguments")
+    if g is None:
+        return lh
+    if want_planes:
+        return lh, gp, gpsi, gphi
+    return lh, gp

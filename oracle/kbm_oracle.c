@@ -1,0 +1,431 @@
+/*
+ * Plain CPU oracle for the shift-and-stack trajectory search of
+ * Smotherman et al., "Sifting Through the Static" (arXiv 2109.03296).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The GPU library never
+ * includes, links or calls it, and it shares no source with the GPU library.
+ *
+ * Everything here is a direct, slow transcription of the definitions, in
+ * FP64 unless stated otherwise:
+ *
+ *   - likelihood planes (Section 3: psi and phi images built from the
+ *     science and variance images with the PSF; masked pixels carry no
+ *     weight);
+ *   - trajectory sums (Section 3: Psi = sum psi_i, Phi = sum phi_i along a
+ *     linear track, nu = Psi / sqrt(Phi));
+ *   - the sigma_G lightcurve filter (Section 3.1, Eqs. 1-5: percentile
+ *     spread times C_{25,75} ~ 0.7413, points farther than n sigma_G from
+ *     the median are dropped, the likelihood is recomputed);
+ *   - the in-line per-pixel top-K of Section 3.2;
+ *   - the bilinear refinement objective and its analytic gradient.
+ *
+ * One deliberate non-FP64 step: the sigma_G keep decision (the per-epoch
+ * nu_i, the order statistics, sigma_G, the threshold and the comparison) is
+ * evaluated in IEEE binary32 with correctly rounded division and square
+ * root.  The paper does not fix a precision; the GPU kernel takes this
+ * decision in binary32, so both sides take it in binary32 and the keep
+ * masks can be compared bit for bit.  Sums and likelihoods stay FP64.
+ *
+ * Build: gcc -O2 -fPIC -shared -fopenmp -ffp-contract=off (no fast-math).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define KBMO_MAX_T 64
+
+int kbmo_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Likelihood planes                                                    */
+/* ------------------------------------------------------------------ */
+
+/* Weight of one input pixel: zero when masked or when the data are not
+ * usable (non-finite value or variance, or variance <= 0), otherwise the
+ * inverse variance.  Zero weight is a *selection*: the caller skips the
+ * term, so a NaN or 1e30 under the mask never enters a product. */
+static double pixel_weight(float sci, float var, uint8_t masked)
+{
+    if (masked) return 0.0;
+    if (!isfinite(sci) || !isfinite(var) || !(var > 0.0f)) return 0.0;
+    return 1.0 / (double)var;
+}
+
+/* psi_i(y,x) = sum_{a,b} P[b+r][a+r] * I_i(y+b,x+a) * w_i(y+b,x+a)
+ * phi_i(y,x) = sum_{a,b} P[b+r][a+r]^2 * w_i(y+b,x+a)
+ * Correlation with the PSF (a matched filter); out-of-image taps add 0. */
+int kbmo_planes(int32_t T, int32_t H, int32_t W, const float *sci,
+                const float *var, const uint8_t *mask, const float *psf,
+                int32_t k, double *psi, double *phi)
+{
+    if (T <= 0 || H <= 0 || W <= 0 || k <= 0 || (k % 2) == 0) return 1;
+    const int r = k / 2;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int t = 0; t < T; ++t) {
+        for (int y = 0; y < H; ++y) {
+            for (int x = 0; x < W; ++x) {
+                double sp = 0.0, sf = 0.0;
+                for (int b = -r; b <= r; ++b) {
+                    const int yy = y + b;
+                    if (yy < 0 || yy >= H) continue;
+                    for (int a = -r; a <= r; ++a) {
+                        const int xx = x + a;
+                        if (xx < 0 || xx >= W) continue;
+                        const size_t q = ((size_t)t * H + yy) * W + xx;
+                        const double w = pixel_weight(sci[q], var[q],
+                                                      mask ? mask[q] : 0);
+                        if (w == 0.0) continue;
+                        const double p = (double)psf[(b + r) * k + (a + r)];
+                        sp += p * ((double)sci[q] * w);
+                        sf += (p * p) * w;
+                    }
+                }
+                const size_t o = ((size_t)t * H + y) * W + x;
+                psi[o] = sp;
+                phi[o] = sf;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Linear trajectories                                                  */
+/* ------------------------------------------------------------------ */
+
+static double earliest(int32_t T, const double *times)
+{
+    double t0 = times[0];
+    for (int i = 1; i < T; ++i)
+        if (times[i] < t0) t0 = times[i];
+    return t0;
+}
+
+/* Integer pixel offset of velocity v at epoch i: round half up of v*t in
+ * FP64, t measured from the earliest epoch.  off[(v*T + i)*2 + {0,1}]. */
+void kbmo_offsets(int32_t T, const double *times, int32_t V, const float *vel,
+                  int32_t *off)
+{
+    const double t0 = earliest(T, times);
+    for (int v = 0; v < V; ++v) {
+        for (int i = 0; i < T; ++i) {
+            const double t = times[i] - t0;
+            const double px = (double)vel[2 * v] * t;
+            const double py = (double)vel[2 * v + 1] * t;
+            off[((size_t)v * T + i) * 2 + 0] = (int32_t)floor(px + 0.5);
+            off[((size_t)v * T + i) * 2 + 1] = (int32_t)floor(py + 0.5);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* sigma_G lightcurve filter (Section 3.1)                              */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double q_lo, q_hi, coeff, n_sigma;
+} sg_params;
+
+/* Nearest-rank selection: the q-quantile of n sorted values is the value
+ * at index floor(q*(n-1) + 1/2). */
+static int quantile_rank(double q, int n)
+{
+    return (int)floor(q * (double)(n - 1) + 0.5);
+}
+
+static int cmp_f32(const void *a, const void *b)
+{
+    const float x = *(const float *)a, y = *(const float *)b;
+    return (x > y) - (x < y);
+}
+
+/* Keep mask over the participating epochs (part[i] != 0).  Binary32
+ * throughout, matching the kernel's precision for this decision. */
+static uint64_t sigmag_keep(int T, const float *ps, const float *ph,
+                            const int *part, const sg_params *p)
+{
+    float nu[KBMO_MAX_T], s[KBMO_MAX_T];
+    int n = 0;
+    for (int i = 0; i < T; ++i) {
+        if (!part[i]) continue;
+        nu[i] = ps[i] / sqrtf(ph[i]);
+        s[n++] = nu[i];
+    }
+    if (n == 0) return 0;
+    qsort(s, (size_t)n, sizeof(float), cmp_f32);
+    const float x_lo = s[quantile_rank(p->q_lo, n)];
+    const float x_md = s[quantile_rank(0.5, n)];
+    const float x_hi = s[quantile_rank(p->q_hi, n)];
+    const float sigma_g = (float)p->coeff * (x_hi - x_lo);
+    const float thr = (float)p->n_sigma * sigma_g;
+    uint64_t keep = 0;
+    for (int i = 0; i < T; ++i)
+        if (part[i] && fabsf(nu[i] - x_md) <= thr) keep |= (uint64_t)1 << i;
+    return keep;
+}
+
+static int usable(float ps, float ph)
+{
+    return ph > 0.0f && isfinite(ph) && isfinite(ps);
+}
+
+/* Standalone filter over n lightcurves [n][T].  phi == NULL means unit
+ * weights (the values in psi are filtered directly).  lh = Psi'/sqrt(Phi')
+ * over the kept epochs, -inf when nothing participates. */
+int kbmo_sigmag(int64_t n, int32_t T, const float *psi, const float *phi,
+                const uint8_t *valid, double q_lo, double q_hi, double coeff,
+                double n_sigma, uint64_t *keep, double *lh)
+{
+    if (T <= 0 || T > KBMO_MAX_T) return 1;
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma};
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n; ++c) {
+        float ps[KBMO_MAX_T], ph[KBMO_MAX_T];
+        int part[KBMO_MAX_T];
+        for (int i = 0; i < T; ++i) {
+            ps[i] = psi[c * T + i];
+            ph[i] = phi ? phi[c * T + i] : 1.0f;
+            part[i] = (!valid || valid[c * T + i]) && usable(ps[i], ph[i]);
+        }
+        const uint64_t kp = sigmag_keep(T, ps, ph, part, &p);
+        double sp = 0.0, sf = 0.0;
+        for (int i = 0; i < T; ++i)
+            if (kp >> i & 1) {
+                sp += (double)ps[i];
+                sf += (double)ph[i];
+            }
+        keep[c] = kp;
+        if (lh) lh[c] = sf > 0.0 ? sp / sqrt(sf) : -INFINITY;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Search with the in-line filter and the per-pixel top-K (Section 3.2) */
+/* ------------------------------------------------------------------ */
+
+/* Ranking: larger filtered likelihood first; equal likelihoods go to the
+ * smaller velocity index. */
+static int ranks_before(double la, int ia, double lb, int ib)
+{
+    return la > lb || (la == lb && ia < ib);
+}
+
+int kbmo_search(int32_t T, int32_t H, int32_t W, const float *psi,
+                const float *phi, const double *times, int32_t V,
+                const float *vel, int32_t K, int32_t min_obs, int32_t sigmag,
+                double q_lo, double q_hi, double coeff, double n_sigma,
+                int32_t x_begin, int32_t y_begin, int32_t x_end, int32_t y_end,
+                double *out_lh, double *out_flux, int32_t *out_vidx,
+                int32_t *out_nobs, uint64_t *out_keep, double *out_lh_raw)
+{
+    if (T <= 0 || T > KBMO_MAX_T || K <= 0 || V <= 0) return 1;
+    if (x_end < x_begin || y_end < y_begin) return 1;
+    const int Wr = x_end - x_begin, Hr = y_end - y_begin;
+    int32_t *off = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)V * T);
+    if (!off) return 3;
+    kbmo_offsets(T, times, V, vel, off);
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma};
+    const size_t plane = (size_t)H * W;
+
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int ry = 0; ry < Hr; ++ry) {
+        for (int rx = 0; rx < Wr; ++rx) {
+            const int y = y_begin + ry, x = x_begin + rx;
+            const size_t o = ((size_t)ry * Wr + rx) * (size_t)K;
+            double *lh = out_lh + o, *fl = out_flux + o;
+            int32_t *vi = out_vidx + o, *no = out_nobs + o;
+            uint64_t *kp = out_keep + o;
+            double *lr = out_lh_raw ? out_lh_raw + o : NULL;
+            for (int s = 0; s < K; ++s) {
+                lh[s] = -INFINITY;
+                fl[s] = 0.0;
+                vi[s] = -1;
+                no[s] = 0;
+                kp[s] = 0;
+                if (lr) lr[s] = -INFINITY;
+            }
+            for (int v = 0; v < V; ++v) {
+                float ps[KBMO_MAX_T], ph[KBMO_MAX_T];
+                int part[KBMO_MAX_T];
+                int n = 0;
+                double sp = 0.0, sf = 0.0;
+                uint64_t valid = 0;
+                for (int i = 0; i < T; ++i) {
+                    const int xx = x + off[((size_t)v * T + i) * 2 + 0];
+                    const int yy = y + off[((size_t)v * T + i) * 2 + 1];
+                    part[i] = 0;
+                    ps[i] = 0.0f;
+                    ph[i] = 0.0f;
+                    if (xx < 0 || xx >= W || yy < 0 || yy >= H) continue;
+                    const size_t q = (size_t)i * plane + (size_t)yy * W + xx;
+                    if (!usable(psi[q], phi[q])) continue;
+                    ps[i] = psi[q];
+                    ph[i] = phi[q];
+                    part[i] = 1;
+                    valid |= (uint64_t)1 << i;
+                    ++n;
+                    sp += (double)ps[i];
+                    sf += (double)ph[i];
+                }
+                if (n == 0 || n < min_obs || !(sf > 0.0)) continue;
+                const double l_raw = sp / sqrt(sf);
+                uint64_t keep = valid;
+                double kp_s = sp, kf_s = sf;
+                if (sigmag) {
+                    keep = sigmag_keep(T, ps, ph, part, &p);
+                    kp_s = 0.0;
+                    kf_s = 0.0;
+                    for (int i = 0; i < T; ++i)
+                        if (keep >> i & 1) {
+                            kp_s += (double)ps[i];
+                            kf_s += (double)ph[i];
+                        }
+                }
+                if (!(kf_s > 0.0)) continue;
+                const double l = kp_s / sqrt(kf_s);
+                if (!isfinite(l)) continue;
+                if (!ranks_before(l, v, lh[K - 1], vi[K - 1])) continue;
+                int s = K - 1;
+                while (s > 0 && ranks_before(l, v, lh[s - 1], vi[s - 1])) {
+                    lh[s] = lh[s - 1];
+                    fl[s] = fl[s - 1];
+                    vi[s] = vi[s - 1];
+                    no[s] = no[s - 1];
+                    kp[s] = kp[s - 1];
+                    if (lr) lr[s] = lr[s - 1];
+                    --s;
+                }
+                lh[s] = l;
+                fl[s] = kp_s / kf_s;
+                vi[s] = v;
+                no[s] = n;
+                kp[s] = keep;
+                if (lr) lr[s] = l_raw;
+            }
+        }
+    }
+    free(off);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Bilinear refinement objective and analytic gradient                  */
+/* ------------------------------------------------------------------ */
+
+static double tap(const float *plane, int H, int W, int x, int y)
+{
+    if (x < 0 || x >= W || y < 0 || y >= H) return 0.0;
+    return (double)plane[(size_t)y * W + x];
+}
+
+/* Bilinear sample with pixel centres at integer coordinates; out-of-image
+ * taps are zero.  Also returns the one-sided (right) partial derivatives in
+ * x and y, the convention that matches floor() at integer coordinates. */
+static double bilinear(const float *plane, int H, int W, double x, double y,
+                       double *ddx, double *ddy)
+{
+    const double fxl = floor(x), fyl = floor(y);
+    const int ix = (int)fxl, iy = (int)fyl;
+    const double fx = x - fxl, fy = y - fyl;
+    const double v00 = tap(plane, H, W, ix, iy);
+    const double v10 = tap(plane, H, W, ix + 1, iy);
+    const double v01 = tap(plane, H, W, ix, iy + 1);
+    const double v11 = tap(plane, H, W, ix + 1, iy + 1);
+    *ddx = (1.0 - fy) * (v10 - v00) + fy * (v11 - v01);
+    *ddy = (1.0 - fx) * (v01 - v00) + fx * (v11 - v10);
+    return (1.0 - fx) * (1.0 - fy) * v00 + fx * (1.0 - fy) * v10 +
+           (1.0 - fx) * fy * v01 + fx * fy * v11;
+}
+
+static void scatter(double *g, int H, int W, double x, double y, double c)
+{
+    const double fxl = floor(x), fyl = floor(y);
+    const int ix = (int)fxl, iy = (int)fyl;
+    const double fx = x - fxl, fy = y - fyl;
+    const int xs[4] = {ix, ix + 1, ix, ix + 1};
+    const int ys[4] = {iy, iy, iy + 1, iy + 1};
+    const double ws[4] = {(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy),
+                          (1.0 - fx) * fy, fx * fy};
+    for (int j = 0; j < 4; ++j) {
+        if (xs[j] < 0 || xs[j] >= W || ys[j] < 0 || ys[j] >= H) continue;
+        g[(size_t)ys[j] * W + xs[j]] += c * ws[j];
+    }
+}
+
+/* L(q) = sum_{i in keep} B(psi_i, x_i, y_i) / sqrt(sum_{i in keep}
+ * B(phi_i, x_i, y_i)), x_i = x0 + vx t_i, y_i = y0 + vy t_i.  L = 0 (and a
+ * zero gradient) when the kept samples carry no phi.  grad_lh == NULL means
+ * forward only; otherwise grad_params = g * dL/d(x0,y0,vx,vy) and g times
+ * dL/dpsi, dL/dphi is added into grad_psi / grad_phi (either may be NULL). */
+int kbmo_refine(int32_t T, int32_t H, int32_t W, const float *psi,
+                const float *phi, const double *times, int64_t n,
+                const float *params, const uint64_t *keep,
+                const double *grad_lh, double *lh, double *grad_params,
+                double *grad_psi, double *grad_phi)
+{
+    if (T <= 0 || T > KBMO_MAX_T || H <= 0 || W <= 0) return 1;
+    const double t0 = earliest(T, times);
+    const size_t plane = (size_t)H * W;
+    for (int64_t c = 0; c < n; ++c) {
+        const double x0 = params[4 * c + 0], y0 = params[4 * c + 1];
+        const double vx = params[4 * c + 2], vy = params[4 * c + 3];
+        const uint64_t km = keep ? keep[c] : ~(uint64_t)0;
+        double sp = 0.0, sf = 0.0;
+        double dpx[KBMO_MAX_T], dpy[KBMO_MAX_T], dfx[KBMO_MAX_T],
+            dfy[KBMO_MAX_T], xs[KBMO_MAX_T], ys[KBMO_MAX_T], ts[KBMO_MAX_T];
+        for (int i = 0; i < T; ++i) {
+            ts[i] = times[i] - t0;
+            xs[i] = x0 + vx * ts[i];
+            ys[i] = y0 + vy * ts[i];
+            if (!(km >> i & 1)) continue;
+            sp += bilinear(psi + i * plane, H, W, xs[i], ys[i], &dpx[i],
+                           &dpy[i]);
+            sf += bilinear(phi + i * plane, H, W, xs[i], ys[i], &dfx[i],
+                           &dfy[i]);
+        }
+        if (!(sf > 0.0)) {
+            lh[c] = 0.0;
+            if (grad_lh && grad_params)
+                for (int j = 0; j < 4; ++j) grad_params[4 * c + j] = 0.0;
+            continue;
+        }
+        const double l = sp / sqrt(sf);
+        lh[c] = l;
+        if (!grad_lh) continue;
+        const double g = grad_lh[c];
+        const double a = 1.0 / sqrt(sf);   /* dL/dPsi */
+        const double b = -l / (2.0 * sf);  /* dL/dPhi */
+        double gx0 = 0.0, gy0 = 0.0, gvx = 0.0, gvy = 0.0;
+        for (int i = 0; i < T; ++i) {
+            if (!(km >> i & 1)) continue;
+            const double dx = a * dpx[i] + b * dfx[i];
+            const double dy = a * dpy[i] + b * dfy[i];
+            gx0 += dx;
+            gy0 += dy;
+            gvx += ts[i] * dx;
+            gvy += ts[i] * dy;
+            if (grad_psi) scatter(grad_psi + i * plane, H, W, xs[i], ys[i], g * a);
+            if (grad_phi) scatter(grad_phi + i * plane, H, W, xs[i], ys[i], g * b);
+        }
+        if (grad_params) {
+            grad_params[4 * c + 0] = g * gx0;
+            grad_params[4 * c + 1] = g * gy0;
+            grad_params[4 * c + 2] = g * gvx;
+            grad_params[4 * c + 3] = g * gvy;
+        }
+    }
+    return 0;
+}
