@@ -1,0 +1,197 @@
+/*
+ * kbm.h - C ABI of the MI355X (gfx950) shift-and-stack trajectory search.
+ *
+ * Method: Smotherman et al., "Sifting Through the Static: Moving Object
+ * Detection in Difference Images" (arXiv 2109.03296), Section 3 (likelihood
+ * planes and trajectory sums), Section 3.1 (sigma_G lightcurve filter,
+ * Eqs. 1-5) and Section 3.2 (in-line GPU filter, per-pixel top-K).
+ *
+ * Conventions shared by every entry point
+ *  - Bulk arrays are caller-owned *device* memory, contiguous, row-major.
+ *    Images are [T][H][W] (epoch, row y, column x).  Small descriptive arrays
+ *    (epoch times, velocity list, PSF) are *host* memory and are read only
+ *    during the call.
+ *  - The library keeps no pointer after a call returns and never frees
+ *    caller memory.
+ *  - Every call validates all arguments on the host first.  On an invalid
+ *    argument nothing is enqueued, the call returns an error code and
+ *    kbm_last_error() describes it.  No HIP call is made before validation
+ *    succeeds, so argument errors are reported even without a GPU.
+ *  - Work is enqueued asynchronously on `stream` (0 = the null stream).
+ *    Launch failures return KBM_ERR_DEVICE with the HIP error text.
+ *  - Bad *data* is not an error: NaN/inf pixels and var <= 0 are treated as
+ *    masked; trajectories with no usable epoch give empty result slots.
+ *  - Times are days; only differences matter (t_i - min_j t_j is used).
+ *    Velocities are pixels/day.  Offsets are floor(v * t + 1/2) in FP64.
+ *  - Calls are reentrant; concurrent calls may use different streams.
+ */
+#ifndef KBM_H
+#define KBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KBM_MAX_EPOCHS 64   /* keep masks are 64-bit */
+#define KBM_MAX_K 16        /* results per pixel */
+#define KBM_MAX_PSF 25      /* odd PSF width limit */
+
+typedef enum {
+    KBM_OK = 0,
+    KBM_ERR_INVALID_ARG = 1,
+    KBM_ERR_UNSUPPORTED = 2,
+    KBM_ERR_OUT_OF_MEMORY = 3,
+    KBM_ERR_DEVICE = 4,
+    KBM_ERR_WORKSPACE = 5
+} kbm_status;
+
+/* Static text for a status code. */
+const char *kbm_status_string(kbm_status s);
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *kbm_last_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int kbm_version(void);
+
+/* One aligned image stack (one CCD over T epochs). */
+typedef struct {
+    int32_t width;       /* W >= 1 */
+    int32_t height;      /* H >= 1 */
+    int32_t num_epochs;  /* T in [1, KBM_MAX_EPOCHS] */
+    const double *times; /* host [T], days, finite */
+} kbm_stack;
+
+/*
+ * kbm_make_planes - likelihood planes of Section 3.
+ *
+ *   w_i(p)   = 0 if mask_i(p) != 0, or sci/var non-finite, or var <= 0;
+ *              otherwise 1 / var_i(p)
+ *   psi_i(p) = sum_{a,b} P[b][a] * sci_i(p + (a-r, b-r)) * w_i(p + (a-r, b-r))
+ *   phi_i(p) = sum_{a,b} P[b][a]^2 * w_i(p + (a-r, b-r))
+ *
+ * i.e. correlation with the PSF (matched filter), r = (psf_k-1)/2, taps
+ * outside the image add nothing.  Masked pixels are removed by selection,
+ * so any value under the mask (NaN, 1e30) never reaches the planes.
+ *
+ *   sci, var : device float [T][H][W]
+ *   mask     : device uint8 [T][H][W], nonzero = masked; may be NULL
+ *   psf      : host float [psf_k][psf_k], row = y, col = x; not normalised
+ *              by the library; psf_k odd, 1 <= psf_k <= KBM_MAX_PSF
+ *   psi, phi : device float [T][H][W], written
+ */
+kbm_status kbm_make_planes(const kbm_stack *s, const float *sci,
+                           const float *var, const uint8_t *mask,
+                           const float *psf, int32_t psf_k, float *psi,
+                           float *phi, hipStream_t stream);
+
+/* Search parameters (Section 3.1 and 3.2). */
+typedef struct {
+    const float *vel;   /* host [num_vel][2] (vx, vy) px/day, finite */
+    int32_t num_vel;    /* >= 1 */
+    int32_t k;          /* results kept per start pixel, 1..KBM_MAX_K */
+    int32_t min_obs;    /* minimum usable epochs, >= 1 */
+    int32_t sigmag;     /* 1 = in-line sigma_G filter, 0 = plain sums */
+    double q_lo, q_hi;  /* quantiles, 0 <= q_lo < q_hi <= 1 (0.25, 0.75) */
+    double coeff;       /* sigma_G = coeff * (x_hi - x_lo), >= 0 (0.7413) */
+    double n_sigma;     /* keep |nu - median| <= n_sigma * sigma_G (2.0) */
+    int32_t x_begin, y_begin, x_end, y_end; /* start pixels [begin, end) */
+} kbm_search_params;
+
+/* Search results, device SoA arrays [Hr][Wr][k] with Hr = y_end - y_begin,
+ * Wr = x_end - x_begin.  Slot order: best first.  Empty slot: lh = -inf,
+ * flux = 0, vel_idx = -1, n_obs = 0, keep = 0, lh_raw = -inf. */
+typedef struct {
+    float *lh;          /* filtered likelihood L' = Psi'/sqrt(Phi') */
+    float *flux;        /* Psi'/Phi' */
+    int32_t *vel_idx;   /* index into the velocity list */
+    int16_t *n_obs;     /* usable epochs before filtering */
+    uint64_t *keep;     /* bit i: epoch i kept by the filter */
+    float *lh_raw;      /* unfiltered likelihood; may be NULL */
+} kbm_results;
+
+/* Bytes of device workspace kbm_search needs for these stacks/params. */
+kbm_status kbm_search_workspace_size(const kbm_stack *stacks,
+                                     const kbm_search_params *p,
+                                     int32_t num_stacks, size_t *bytes);
+
+/*
+ * kbm_search - exhaustive linear-trajectory search with the in-line sigma_G
+ * filter and per-pixel top-K (Section 3, 3.1, 3.2).
+ *
+ * For start pixel p and velocity v, epoch i is usable when p + off_i(v) lies
+ * in the image and phi_i > 0 there (and psi, phi are finite).  n_obs =
+ * number of usable epochs.  Plain sums Psi, Phi over usable epochs give
+ * lh_raw = Psi/sqrt(Phi).  With sigmag = 1, over the usable epochs:
+ * nu_i = psi_i / sqrt(phi_i); x_q = sorted(nu)[floor(q (n_obs-1) + 1/2)] for
+ * q in {q_lo, 1/2, q_hi}; sigma_G = coeff (x_hi - x_lo); epoch i is kept iff
+ * |nu_i - x_1/2| <= n_sigma sigma_G (this decision is taken in binary32);
+ * L' = Psi'/sqrt(Phi') over kept epochs.  With sigmag = 0, L' = lh_raw and
+ * keep = usable.  Trajectories with n_obs < min_obs or non-finite L' are
+ * dropped.  Each start pixel keeps its k best by L' (ties: smaller velocity
+ * index first).
+ *
+ *   stacks, p, out : host arrays [num_stacks]
+ *   psi, phi       : host arrays [num_stacks] of device float [T][H][W]
+ *   workspace      : device, >= kbm_search_workspace_size bytes
+ */
+kbm_status kbm_search(const kbm_stack *stacks, const float *const *psi,
+                      const float *const *phi, const kbm_search_params *p,
+                      kbm_results *out, int32_t num_stacks, void *workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * kbm_sigmag_filter - the sigma_G lightcurve filter of Section 3.1 on n
+ * independent lightcurves, with the same rule and precision as kbm_search.
+ *
+ *   psi_curve  : device float [n][T]
+ *   phi_curve  : device float [n][T]; NULL means phi = 1 (the values in
+ *                psi_curve are filtered directly and L' = sum / sqrt(count))
+ *   valid      : device uint8 [n][T], 0 = epoch absent; may be NULL
+ *   keep       : device uint64 [n], written
+ *   lh_filtered: device float [n] (L', -inf if nothing participates); may
+ *                be NULL
+ * An epoch participates when valid != 0, phi > 0 and psi, phi are finite.
+ * T in [1, KBM_MAX_EPOCHS]; n >= 0.
+ */
+kbm_status kbm_sigmag_filter(const float *psi_curve, const float *phi_curve,
+                             const uint8_t *valid, int64_t n, int32_t T,
+                             double q_lo, double q_hi, double coeff,
+                             double n_sigma, uint64_t *keep,
+                             float *lh_filtered, hipStream_t stream);
+
+/*
+ * kbm_refine - bilinear trajectory likelihood and its adjoint, used to
+ * refine candidates to sub-pixel start positions and velocities.  (Not a
+ * step of the paper; it continues Section 3's likelihood to real-valued
+ * positions.)
+ *
+ * x_i = x0 + vx t_i, y_i = y0 + vy t_i (FP64 positions), B(P, x, y) the
+ * bilinear sample with pixel centres at integer coordinates and zero
+ * outside the image;  L = sum_{i in keep} B(psi_i) / sqrt(sum B(phi_i)),
+ * L = 0 when the kept samples carry no phi.
+ *
+ *   psi, phi    : device float [T][H][W]
+ *   params      : device float [n][4] (x0, y0, vx, vy)
+ *   keep        : device uint64 [n]; NULL = all epochs
+ *   lh          : device float [n], written
+ *   grad_lh     : device float [n] upstream gradient g; NULL = forward only
+ *   grad_params : device float [n][4], overwritten with g * dL/dparams
+ *                 (required when grad_lh != NULL)
+ *   grad_psi, grad_phi : device float [T][H][W], g * dL/dplane is ADDED
+ *                 (float atomics, order not deterministic); may be NULL
+ * Derivatives at integer coordinates are the right-sided ones.
+ */
+kbm_status kbm_refine(const kbm_stack *s, const float *psi, const float *phi,
+                      int64_t n, const float *params, const uint64_t *keep,
+                      float *lh, const float *grad_lh, float *grad_params,
+                      float *grad_psi, float *grad_phi, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KBM_H */

@@ -1,0 +1,343 @@
+"""Python binding of libkbm (MI355X shift-and-stack search).
+
+Argument marshalling only: every step of the search runs in the HIP kernels
+of ``libkbm.so``; this module checks tensor shapes/dtypes, allocates output
+tensors, and passes raw device pointers plus the current HIP stream through
+the C ABI declared in ``include/kbm.h``.  PyTorch supplies device memory and
+streams.  There is no CPU fallback: without the built library every call
+raises.
+
+Method: Smotherman et al., arXiv 2109.03296, Section 3 (likelihood planes,
+trajectory sums), 3.1 (sigma_G filter) and 3.2 (in-line filter, per-pixel
+top-K).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+__all__ = [
+    "KbmError", "lib", "make_planes", "search", "search_batched",
+    "search_workspace_size", "sigmag_filter", "refine_forward",
+    "refine_backward", "TrajLH", "SearchParams", "MAX_EPOCHS", "MAX_K",
+    "MAX_PSF",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkbm.so")
+MAX_EPOCHS, MAX_K, MAX_PSF = 64, 16, 25
+
+_lock = threading.Lock()
+_lib = None
+
+
+class KbmError(RuntimeError):
+    def __init__(self, func, status, detail):
+        super().__init__(f"{func}: {status} ({detail})")
+        self.func, self.status, self.detail = func, status, detail
+
+
+class _Stack(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32),
+                ("num_epochs", C.c_int32), ("times", C.c_void_p)]
+
+
+class _SearchParams(C.Structure):
+    _fields_ = [("vel", C.c_void_p), ("num_vel", C.c_int32), ("k", C.c_int32),
+                ("min_obs", C.c_int32), ("sigmag", C.c_int32),
+                ("q_lo", C.c_double), ("q_hi", C.c_double),
+                ("coeff", C.c_double), ("n_sigma", C.c_double),
+                ("x_begin", C.c_int32), ("y_begin", C.c_int32),
+                ("x_end", C.c_int32), ("y_end", C.c_int32)]
+
+
+class _Results(C.Structure):
+    _fields_ = [("lh", C.c_void_p), ("flux", C.c_void_p),
+                ("vel_idx", C.c_void_p), ("n_obs", C.c_void_p),
+                ("keep", C.c_void_p), ("lh_raw", C.c_void_p)]
+
+
+def lib():
+    """Load libkbm.so (building it first only if it does not exist)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            from . import build as _build
+            _build.build()
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libkbm.so is missing and could not be built")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.kbm_status_string.restype = C.c_char_p
+        L.kbm_status_string.argtypes = [C.c_int]
+        L.kbm_last_error.restype = C.c_char_p
+        L.kbm_version.restype = C.c_int
+        L.kbm_make_planes.argtypes = [P, P, P, P, P, i32, P, P, P]
+        L.kbm_search_workspace_size.argtypes = [P, P, i32, P]
+        L.kbm_search.argtypes = [P, P, P, P, P, i32, P, C.c_size_t, P]
+        L.kbm_sigmag_filter.argtypes = [P, P, P, i64, i32, f64, f64, f64, f64,
+                                        P, P, P]
+        L.kbm_refine.argtypes = [P, P, P, i64, P, P, P, P, P, P, P, P]
+        _lib = L
+        return L
+
+
+def _check(func, status):
+    if status != 0:
+        L = lib()
+        raise KbmError(func, L.kbm_status_string(status).decode(),
+                       L.kbm_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _stack(T, H, W, times):
+    times = _host(times, np.float64).reshape(-1)
+    if times.shape[0] != T:
+        raise ValueError(f"times has {times.shape[0]} entries, planes have {T}")
+    return _Stack(W, H, T, times.ctypes.data), times
+
+
+def make_planes(sci, var, mask, psf, times=None, stream=None):
+    """psi, phi = correlation of I*w with the PSF and of w with PSF^2
+    (w = inverse variance, zero where masked or unusable).  ``sci``/``var``
+    are float32 ``[T][H][W]`` device tensors, ``mask`` uint8 or None, ``psf``
+    a host ``[k][k]`` array."""
+    T, H, W = sci.shape
+    _dev(sci, torch.float32, "sci")
+    _dev(var, torch.float32, "var", sci.shape)
+    if mask is not None:
+        _dev(mask, torch.uint8, "mask", sci.shape)
+    psf = _host(psf, np.float32)
+    if psf.ndim != 2 or psf.shape[0] != psf.shape[1]:
+        raise ValueError("psf must be square")
+    st, _t = _stack(T, H, W, np.zeros(T) if times is None else times)
+    psi = torch.empty_like(sci)
+    phi = torch.empty_like(sci)
+    _check("kbm_make_planes", lib().kbm_make_planes(
+        C.byref(st), _ptr(sci), _ptr(var), _ptr(mask),
+        psf.ctypes.data_as(C.c_void_p), psf.shape[0], _ptr(psi), _ptr(phi),
+        _stream(stream)))
+    return psi, phi
+
+
+@dataclass
+class SearchParams:
+    k: int = 8
+    min_obs: int = 1
+    sigmag: bool = True
+    q_lo: float = 0.25
+    q_hi: float = 0.75
+    coeff: float = 0.7413
+    n_sigma: float = 2.0
+    region: Optional[Sequence[int]] = None   # (x_begin, y_begin, x_end, y_end)
+
+
+def _params(p: SearchParams, vels, W, H):
+    vels = _host(vels, np.float32).reshape(-1, 2)
+    x0, y0, x1, y1 = p.region if p.region is not None else (0, 0, W, H)
+    sp = _SearchParams(vels.ctypes.data, vels.shape[0], int(p.k),
+                       int(p.min_obs), int(bool(p.sigmag)), float(p.q_lo),
+                       float(p.q_hi), float(p.coeff), float(p.n_sigma),
+                       int(x0), int(y0), int(x1), int(y1))
+    return sp, vels
+
+
+def _alloc_results(Hr, Wr, k, device, want_lh_raw):
+    shape = (Hr, Wr, k)
+    out = dict(lh=torch.empty(shape, dtype=torch.float32, device=device),
+               flux=torch.empty(shape, dtype=torch.float32, device=device),
+               vel_idx=torch.empty(shape, dtype=torch.int32, device=device),
+               n_obs=torch.empty(shape, dtype=torch.int16, device=device),
+               keep=torch.empty(shape, dtype=torch.int64, device=device))
+    out["lh_raw"] = (torch.empty(shape, dtype=torch.float32, device=device)
+                     if want_lh_raw else None)
+    r = _Results(out["lh"].data_ptr(), out["flux"].data_ptr(),
+                 out["vel_idx"].data_ptr(), out["n_obs"].data_ptr(),
+                 out["keep"].data_ptr(),
+                 out["lh_raw"].data_ptr() if want_lh_raw else None)
+    return out, r
+
+
+def search_workspace_size(shapes_times_vels, params: Sequence[SearchParams]) -> int:
+    """Workspace bytes for stacks given as ``[(T, H, W, times, vels), ...]``."""
+    n = len(shapes_times_vels)
+    stacks = (_Stack * n)()
+    ps = (_SearchParams * n)()
+    keep = []
+    for j, ((T, H, W, times, vels), p) in enumerate(zip(shapes_times_vels, params)):
+        stacks[j], t = _stack(T, H, W, times)
+        ps[j], v = _params(p, vels, W, H)
+        keep += [t, v]
+    nbytes = C.c_size_t(0)
+    _check("kbm_search_workspace_size", lib().kbm_search_workspace_size(
+        stacks, ps, n, C.byref(nbytes)))
+    return int(nbytes.value)
+
+
+def search_batched(items, want_lh_raw=True, workspace=None, stream=None):
+    """Search several independent stacks in one call.
+
+    ``items`` is a list of dicts with keys psi, phi, times, vels, params
+    (a SearchParams).  Returns one result dict per stack."""
+    n = len(items)
+    stacks = (_Stack * n)()
+    ps = (_SearchParams * n)()
+    psi_p = (C.c_void_p * n)()
+    phi_p = (C.c_void_p * n)()
+    res = (_Results * n)()
+    outs, hold = [], []
+    for j, it in enumerate(items):
+        psi, phi = it["psi"], it["phi"]
+        _dev(psi, torch.float32, "psi")
+        _dev(phi, torch.float32, "phi", psi.shape)
+        T, H, W = psi.shape
+        stacks[j], t = _stack(T, H, W, it["times"])
+        p = it.get("params") or SearchParams()
+        ps[j], v = _params(p, it["vels"], W, H)
+        hold += [t, v]
+        psi_p[j] = psi.data_ptr()
+        phi_p[j] = phi.data_ptr()
+        x0, y0, x1, y1 = p.region if p.region is not None else (0, 0, W, H)
+        o, r = _alloc_results(y1 - y0, x1 - x0, p.k, psi.device, want_lh_raw)
+        outs.append(o)
+        res[j] = r
+    L = lib()
+    nbytes = C.c_size_t(0)
+    _check("kbm_search_workspace_size",
+           L.kbm_search_workspace_size(stacks, ps, n, C.byref(nbytes)))
+    if workspace is None or workspace.numel() < nbytes.value:
+        workspace = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8,
+                                device=items[0]["psi"].device)
+    _check("kbm_search", L.kbm_search(stacks, psi_p, phi_p, ps, res, n,
+                                      _ptr(workspace), workspace.numel(),
+                                      _stream(stream)))
+    return outs
+
+
+def search(psi, phi, times, vels, params: Optional[SearchParams] = None,
+           want_lh_raw=True, workspace=None, stream=None, **kw):
+    """Search one stack; ``kw`` may override SearchParams fields."""
+    p = params or SearchParams()
+    if kw:
+        p = SearchParams(**{**p.__dict__, **kw})
+    return search_batched([dict(psi=psi, phi=phi, times=times, vels=vels,
+                                params=p)], want_lh_raw, workspace, stream)[0]
+
+
+def sigmag_filter(psi_curve, phi_curve=None, valid=None, q_lo=0.25,
+                  q_hi=0.75, coeff=0.7413, n_sigma=2.0, want_lh=True,
+                  stream=None):
+    """sigma_G filter over ``[n][T]`` lightcurves; returns (keep int64 bit
+    masks, filtered likelihood float32 or None)."""
+    _dev(psi_curve, torch.float32, "psi_curve")
+    n, T = psi_curve.shape
+    if phi_curve is not None:
+        _dev(phi_curve, torch.float32, "phi_curve", psi_curve.shape)
+    if valid is not None:
+        _dev(valid, torch.uint8, "valid", psi_curve.shape)
+    keep = torch.empty(n, dtype=torch.int64, device=psi_curve.device)
+    lh = torch.empty(n, dtype=torch.float32, device=psi_curve.device) if want_lh else None
+    _check("kbm_sigmag_filter", lib().kbm_sigmag_filter(
+        _ptr(psi_curve), _ptr(phi_curve), _ptr(valid), n, T, q_lo, q_hi,
+        coeff, n_sigma, _ptr(keep), _ptr(lh), _stream(stream)))
+    return keep, lh
+
+
+def refine_forward(psi, phi, times, params, keep=None, stream=None):
+    """Bilinear likelihood L for ``[n][4]`` params (x0, y0, vx, vy)."""
+    _dev(psi, torch.float32, "psi")
+    _dev(phi, torch.float32, "phi", psi.shape)
+    _dev(params, torch.float32, "params")
+    T, H, W = psi.shape
+    n = params.shape[0]
+    if keep is not None:
+        _dev(keep, torch.int64, "keep", (n,))
+    st, _t = _stack(T, H, W, times)
+    lh = torch.empty(n, dtype=torch.float32, device=psi.device)
+    _check("kbm_refine", lib().kbm_refine(
+        C.byref(st), _ptr(psi), _ptr(phi), n, _ptr(params), _ptr(keep),
+        _ptr(lh), None, None, None, None, _stream(stream)))
+    return lh
+
+
+def refine_backward(psi, phi, times, params, grad_lh, keep=None,
+                    grad_psi=None, grad_phi=None, stream=None):
+    """(lh, g * dL/dparams); g * dL/dpsi, g * dL/dphi are added into
+    grad_psi / grad_phi when given."""
+    _dev(psi, torch.float32, "psi")
+    _dev(phi, torch.float32, "phi", psi.shape)
+    _dev(params, torch.float32, "params")
+    T, H, W = psi.shape
+    n = params.shape[0]
+    _dev(grad_lh, torch.float32, "grad_lh", (n,))
+    if keep is not None:
+        _dev(keep, torch.int64, "keep", (n,))
+    for g, nm in ((grad_psi, "grad_psi"), (grad_phi, "grad_phi")):
+        if g is not None:
+            _dev(g, torch.float32, nm, psi.shape)
+    st, _t = _stack(T, H, W, times)
+    lh = torch.empty(n, dtype=torch.float32, device=psi.device)
+    gp = torch.empty((n, 4), dtype=torch.float32, device=psi.device)
+    _check("kbm_refine", lib().kbm_refine(
+        C.byref(st), _ptr(psi), _ptr(phi), n, _ptr(params), _ptr(keep),
+        _ptr(lh), _ptr(grad_lh), _ptr(gp), _ptr(grad_psi), _ptr(grad_phi),
+        _stream(stream)))
+    return lh, gp
+
+
+class TrajLH(torch.autograd.Function):
+    """L(params, psi, phi) through the bilinear adjoint kernel.
+
+    ``TrajLH.apply(params, psi, phi, times, keep)``; gradients flow to
+    params and, if they require grad, to psi and phi."""
+
+    @staticmethod
+    def forward(ctx, params, psi, phi, times, keep=None):
+        params = params.contiguous()
+        ctx.save_for_backward(params, psi, phi, keep)
+        ctx.times = times
+        return refine_forward(psi, phi, times, params, keep)
+
+    @staticmethod
+    def backward(ctx, grad_lh):
+        params, psi, phi, keep = ctx.saved_tensors
+        need_psi, need_phi = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        gpsi = torch.zeros_like(psi) if need_psi else None
+        gphi = torch.zeros_like(phi) if need_phi else None
+        _, gp = refine_backward(psi, phi, ctx.times, params,
+                                grad_lh.contiguous().float(), keep, gpsi, gphi)
+        return gp, gpsi, gphi, None, None

@@ -1,0 +1,161 @@
+// Internal helpers shared by the kbm HIP translation units: error
+// reporting, argument checks, and the sigma_G device code used by both the
+// fused search kernel and the standalone filter kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "kbm.h"
+
+namespace kbm {
+
+// ---------------------------------------------------------------------
+// Host-side error handling
+// ---------------------------------------------------------------------
+void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+#define KBM_REQUIRE(cond, code, ...)          \
+    do {                                      \
+        if (!(cond)) {                        \
+            ::kbm::set_error(__VA_ARGS__);    \
+            return (code);                    \
+        }                                     \
+    } while (0)
+
+#define KBM_HIP(call)                                                       \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) {                                             \
+            ::kbm::set_error("%s failed: %s", #call, hipGetErrorString(e_)); \
+            return KBM_ERR_DEVICE;                                          \
+        }                                                                   \
+    } while (0)
+
+// Check that the last launch was accepted by the runtime.
+#define KBM_LAUNCHED(name)                                                 \
+    do {                                                                   \
+        hipError_t e_ = hipGetLastError();                                 \
+        if (e_ != hipSuccess) {                                            \
+            ::kbm::set_error("launch of %s failed: %s", name,              \
+                             hipGetErrorString(e_));                       \
+            return KBM_ERR_DEVICE;                                         \
+        }                                                                  \
+    } while (0)
+
+kbm_status check_stack(const kbm_stack *s, const char *what);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Asynchronous copy of a small host table to device memory on `stream`
+// through a pinned staging buffer (safe to free `src` on return).
+kbm_status stage_to_device(void *dst, const void *src, size_t bytes,
+                           hipStream_t stream);
+
+// ---------------------------------------------------------------------
+// Quantile ranks: nearest-rank selection floor(q (n-1) + 1/2) in FP64,
+// tabulated on the host for every usable-epoch count n in [1, 64].
+// ---------------------------------------------------------------------
+struct RankTable {
+    uint8_t lo[KBM_MAX_EPOCHS + 1];
+    uint8_t md[KBM_MAX_EPOCHS + 1];
+    uint8_t hi[KBM_MAX_EPOCHS + 1];
+};
+
+RankTable make_rank_table(double q_lo, double q_hi);
+
+kbm_status check_sigmag_params(double q_lo, double q_hi, double coeff,
+                               double n_sigma);
+
+// ---------------------------------------------------------------------
+// Device code: fixed-size sorting network and rank selection
+// ---------------------------------------------------------------------
+
+// Batcher's odd-even merge sort on N registers (any N), fully unrolled.
+// All indices are compile-time constants, so the array stays in VGPRs and
+// every comparator is one v_min_f32 + one v_max_f32.
+template <int N>
+__device__ __forceinline__ void sort_network(float (&a)[N]) {
+#pragma unroll
+    for (int p = 1; p < N; p <<= 1) {
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1) {
+#pragma unroll
+            for (int j = k % p; j + k < N; j += 2 * k) {
+#pragma unroll
+                for (int i = 0; i < k; ++i) {
+                    if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const float x = a[i + j], y = a[i + j + k];
+                        a[i + j] = fminf(x, y);
+                        a[i + j + k] = fmaxf(x, y);
+                    }
+                }
+            }
+        }
+    }
+}
+
+constexpr int next_pow2(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// a[r] for a runtime index r in [0, N): a binary tree of selects on the bits
+// of r (P-1 v_cndmask for P = next_pow2(N)).
+template <int N>
+__device__ __forceinline__ float select_rank(const float (&a)[N], int r) {
+    constexpr int P = next_pow2(N);
+    float t[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) t[j] = a[j < N ? j : N - 1];
+#pragma unroll
+    for (int w = P / 2, b = 0; w >= 1; w /= 2, ++b) {
+        const bool bit = (r >> b) & 1;
+#pragma unroll
+        for (int j = 0; j < w; ++j) t[j] = bit ? t[2 * j + 1] : t[2 * j];
+    }
+    return t[0];
+}
+
+// sigma_G keep decision (Section 3.1) for one lightcurve held in registers.
+// nu[i] is psi_i/sqrt(phi_i) for usable epochs and NaN otherwise; n is the
+// number of usable epochs (>= 1).  Binary32 throughout, no contraction:
+//   x_q   = sorted usable nu at rank r_q(n)
+//   sigma = coeff * (x_hi - x_lo);  thr = n_sigma * sigma
+//   keep  = |nu_i - x_md| <= thr   (false for NaN, i.e. unusable epochs)
+// Writes the keep flags into kf[] and returns them as a 64-bit mask.
+template <int N>
+__device__ __forceinline__ uint64_t sigmag_keep(const float (&nu)[N], int n,
+                                                const RankTable &rt,
+                                                float coeff, float n_sigma,
+                                                bool (&kf)[N]) {
+#pragma clang fp contract(off)
+    float s[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = (nu[i] == nu[i]) ? nu[i] : INFINITY;
+    sort_network<N>(s);
+    const float x_lo = select_rank<N>(s, rt.lo[n]);
+    const float x_md = select_rank<N>(s, rt.md[n]);
+    const float x_hi = select_rank<N>(s, rt.hi[n]);
+    const float sigma = coeff * (x_hi - x_lo);
+    const float thr = n_sigma * sigma;
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        kf[i] = fabsf(nu[i] - x_md) <= thr;
+        if (i < 32)
+            lo |= kf[i] ? (1u << i) : 0u;
+        else
+            hi |= kf[i] ? (1u << (i - 32)) : 0u;
+    }
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+}  // namespace kbm

@@ -1,0 +1,185 @@
+// Bilinear trajectory likelihood and its adjoint (refinement of search
+// candidates to sub-pixel start positions and velocities).
+//
+// One lane per candidate.  Positions x_i = x0 + vx t_i are formed in FP64
+// (a float32 position at x ~ 4000 px would carry ~2e-4 px of rounding), the
+// taps and weights in binary32.  The forward pass accumulates the bilinear
+// samples of psi and phi over the kept epochs; the backward pass (only when
+// an upstream gradient is given) revisits the same taps, forms
+// dL/dx_i = dPsi/dx_i / sqrt(Phi) - L/(2 Phi) dPhi/dx_i, chains through
+// dx_i/dx0 = 1 and dx_i/dvx = t_i, and scatter-adds g/sqrt(Phi) * w_tap into
+// dL/dpsi and -g L/(2 Phi) * w_tap into dL/dphi with float atomics.
+#include "kbm_internal.h"
+
+namespace kbm {
+namespace {
+
+struct RefineArgs {
+    const float *psi;
+    const float *phi;
+    const float *params;
+    const uint64_t *keep;
+    float *lh;
+    const float *grad_lh;
+    float *grad_params;
+    float *grad_psi;
+    float *grad_phi;
+    int64_t n;
+    int W, H, T;
+    double t[KBM_MAX_EPOCHS];
+};
+
+struct Taps {
+    int ix, iy;
+    float fx, fy;
+    bool any;  // at least one tap inside the image
+};
+
+__device__ __forceinline__ Taps taps_at(const RefineArgs &a, double x0,
+                                        double vx, double y0, double vy,
+                                        double t) {
+#pragma clang fp contract(off)
+    const double x = x0 + vx * t;
+    const double y = y0 + vy * t;
+    const double fxl = floor(x), fyl = floor(y);
+    Taps p;
+    p.any = fxl >= -1.0 && fxl <= (double)(a.W - 1) && fyl >= -1.0 &&
+            fyl <= (double)(a.H - 1);
+    p.ix = p.any ? (int)fxl : 0;
+    p.iy = p.any ? (int)fyl : 0;
+    p.fx = p.any ? (float)(x - fxl) : 0.0f;
+    p.fy = p.any ? (float)(y - fyl) : 0.0f;
+    return p;
+}
+
+__device__ __forceinline__ float tap(const float *plane, int W, int H, int x,
+                                     int y) {
+    return ((unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H)
+               ? plane[(size_t)y * W + x]
+               : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void refine_kernel(RefineArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    const double x0 = a.params[4 * c + 0], y0 = a.params[4 * c + 1];
+    const double vx = a.params[4 * c + 2], vy = a.params[4 * c + 3];
+    const uint64_t km = a.keep ? a.keep[c] : ~(uint64_t)0;
+    const size_t HW = (size_t)a.W * a.H;
+
+    float Ps = 0.0f, Fs = 0.0f;
+    for (int i = 0; i < a.T; ++i) {
+        if (!((km >> i) & 1)) continue;
+        const Taps p = taps_at(a, x0, vx, y0, vy, a.t[i]);
+        if (!p.any) continue;
+        const float *ps = a.psi + i * HW;
+        const float *ph = a.phi + i * HW;
+        const float w00 = (1.0f - p.fx) * (1.0f - p.fy), w10 = p.fx * (1.0f - p.fy);
+        const float w01 = (1.0f - p.fx) * p.fy, w11 = p.fx * p.fy;
+        Ps += w00 * tap(ps, a.W, a.H, p.ix, p.iy) + w10 * tap(ps, a.W, a.H, p.ix + 1, p.iy) +
+              w01 * tap(ps, a.W, a.H, p.ix, p.iy + 1) + w11 * tap(ps, a.W, a.H, p.ix + 1, p.iy + 1);
+        Fs += w00 * tap(ph, a.W, a.H, p.ix, p.iy) + w10 * tap(ph, a.W, a.H, p.ix + 1, p.iy) +
+              w01 * tap(ph, a.W, a.H, p.ix, p.iy + 1) + w11 * tap(ph, a.W, a.H, p.ix + 1, p.iy + 1);
+    }
+    if (!(Fs > 0.0f)) {
+        a.lh[c] = 0.0f;
+        if (a.grad_lh) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a.grad_params[4 * c + j] = 0.0f;
+        }
+        return;
+    }
+    const float L = Ps / sqrtf(Fs);
+    a.lh[c] = L;
+    if (!a.grad_lh) return;
+
+    const float g = a.grad_lh[c];
+    const float A = 1.0f / sqrtf(Fs);
+    const float B = -L / (2.0f * Fs);
+    float gx0 = 0.0f, gy0 = 0.0f, gvx = 0.0f, gvy = 0.0f;
+    for (int i = 0; i < a.T; ++i) {
+        if (!((km >> i) & 1)) continue;
+        const Taps p = taps_at(a, x0, vx, y0, vy, a.t[i]);
+        if (!p.any) continue;
+        const float *ps = a.psi + i * HW;
+        const float *ph = a.phi + i * HW;
+        const float s00 = tap(ps, a.W, a.H, p.ix, p.iy), s10 = tap(ps, a.W, a.H, p.ix + 1, p.iy);
+        const float s01 = tap(ps, a.W, a.H, p.ix, p.iy + 1), s11 = tap(ps, a.W, a.H, p.ix + 1, p.iy + 1);
+        const float f00 = tap(ph, a.W, a.H, p.ix, p.iy), f10 = tap(ph, a.W, a.H, p.ix + 1, p.iy);
+        const float f01 = tap(ph, a.W, a.H, p.ix, p.iy + 1), f11 = tap(ph, a.W, a.H, p.ix + 1, p.iy + 1);
+        const float dpx = (1.0f - p.fy) * (s10 - s00) + p.fy * (s11 - s01);
+        const float dpy = (1.0f - p.fx) * (s01 - s00) + p.fx * (s11 - s10);
+        const float dfx = (1.0f - p.fy) * (f10 - f00) + p.fy * (f11 - f01);
+        const float dfy = (1.0f - p.fx) * (f01 - f00) + p.fx * (f11 - f10);
+        const float dx = A * dpx + B * dfx;
+        const float dy = A * dpy + B * dfy;
+        const float ti = (float)a.t[i];
+        gx0 += dx;
+        gy0 += dy;
+        gvx += ti * dx;
+        gvy += ti * dy;
+        if (a.grad_psi || a.grad_phi) {
+            const float w[4] = {(1.0f - p.fx) * (1.0f - p.fy), p.fx * (1.0f - p.fy),
+                                (1.0f - p.fx) * p.fy, p.fx * p.fy};
+            const int xs[4] = {p.ix, p.ix + 1, p.ix, p.ix + 1};
+            const int ys[4] = {p.iy, p.iy, p.iy + 1, p.iy + 1};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if ((unsigned)xs[j] >= (unsigned)a.W || (unsigned)ys[j] >= (unsigned)a.H) continue;
+                const size_t q = i * HW + (size_t)ys[j] * a.W + xs[j];
+                if (a.grad_psi) unsafeAtomicAdd(a.grad_psi + q, g * A * w[j]);
+                if (a.grad_phi) unsafeAtomicAdd(a.grad_phi + q, g * B * w[j]);
+            }
+        }
+    }
+    a.grad_params[4 * c + 0] = g * gx0;
+    a.grad_params[4 * c + 1] = g * gy0;
+    a.grad_params[4 * c + 2] = g * gvx;
+    a.grad_params[4 * c + 3] = g * gvy;
+}
+
+}  // namespace
+}  // namespace kbm
+
+extern "C" kbm_status kbm_refine(const kbm_stack *s, const float *psi,
+                                 const float *phi, int64_t n,
+                                 const float *params, const uint64_t *keep,
+                                 float *lh, const float *grad_lh,
+                                 float *grad_params, float *grad_psi,
+                                 float *grad_phi, hipStream_t stream) {
+    using namespace kbm;
+    clear_error();
+    kbm_status st = check_stack(s, "kbm_refine");
+    if (st != KBM_OK) return st;
+    KBM_REQUIRE(n >= 0, KBM_ERR_INVALID_ARG, "kbm_refine: n = %lld must be >= 0",
+                (long long)n);
+    KBM_REQUIRE(n == 0 || (psi && phi && params && lh), KBM_ERR_INVALID_ARG,
+                "kbm_refine: psi, phi, params and lh must be non-NULL");
+    KBM_REQUIRE(grad_lh == nullptr || grad_params != nullptr || n == 0,
+                KBM_ERR_INVALID_ARG,
+                "kbm_refine: grad_params is required with grad_lh");
+    KBM_REQUIRE((n + 255) / 256 < ((int64_t)1 << 31), KBM_ERR_UNSUPPORTED,
+                "kbm_refine: n = %lld too large", (long long)n);
+    if (n == 0) return KBM_OK;
+    RefineArgs a{};
+    a.psi = psi;
+    a.phi = phi;
+    a.params = params;
+    a.keep = keep;
+    a.lh = lh;
+    a.grad_lh = grad_lh;
+    a.grad_params = grad_params;
+    a.grad_psi = grad_lh ? grad_psi : nullptr;
+    a.grad_phi = grad_lh ? grad_phi : nullptr;
+    a.n = n;
+    a.W = s->width;
+    a.H = s->height;
+    a.T = s->num_epochs;
+    double t0 = s->times[0];
+    for (int i = 1; i < a.T; ++i) t0 = std::min(t0, s->times[i]);
+    for (int i = 0; i < a.T; ++i) a.t[i] = s->times[i] - t0;
+    hipLaunchKernelGGL(refine_kernel, dim3((unsigned)((n + 255) / 256)),
+                       dim3(256), 0, stream, a);
+    KBM_LAUNCHED("refine_kernel");
+    return KBM_OK;
+}

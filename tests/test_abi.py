@@ -1,0 +1,146 @@
+"""The C ABI library loads without a GPU, exports every entry point that
+include/kbm.h declares, and rejects bad arguments on the host before any
+HIP call."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(kbm_\w+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2109_03296_amd as kbm
+    return kbm.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert {"kbm_make_planes", "kbm_search", "kbm_search_workspace_size",
+            "kbm_sigmag_filter", "kbm_refine", "kbm_status_string",
+            "kbm_last_error", "kbm_version"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    assert L.kbm_status_string(0) == b"ok"
+    assert L.kbm_status_string(1) == b"invalid argument"
+    assert L.kbm_status_string(5) == b"workspace too small"
+    assert L.kbm_version() >= 100
+
+
+def _stack(T=5, H=8, W=9, times=None):
+    import paper_2109_03296_amd as kbm
+    t = np.linspace(0, 1, T) if times is None else np.asarray(times, np.float64)
+    return kbm._Stack(W, H, T, t.ctypes.data), t
+
+
+FAKE = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+def test_make_planes_validation(L):
+    st, t = _stack()
+    psf = np.ones((3, 3), np.float32)
+    pp = psf.ctypes.data_as(C.c_void_p)
+    assert L.kbm_make_planes(None, FAKE, FAKE, None, pp, 3, FAKE, FAKE, None) == 1
+    assert L.kbm_make_planes(C.byref(st), FAKE, FAKE, None, pp, 4, FAKE, FAKE, None) == 1
+    assert b"odd" in L.kbm_last_error()
+    big = np.ones((27, 27), np.float32)
+    assert L.kbm_make_planes(C.byref(st), FAKE, FAKE, None,
+                             big.ctypes.data_as(C.c_void_p), 27, FAKE, FAKE, None) == 2
+    assert L.kbm_make_planes(C.byref(st), None, FAKE, None, pp, 3, FAKE, FAKE, None) == 1
+    st65, t65 = _stack(T=65)
+    assert L.kbm_make_planes(C.byref(st65), FAKE, FAKE, None, pp, 3, FAKE, FAKE, None) == 1
+    stn, tn = _stack(times=[0.0, float("nan"), 1.0, 2.0, 3.0])
+    assert L.kbm_make_planes(C.byref(stn), FAKE, FAKE, None, pp, 3, FAKE, FAKE, None) == 1
+    assert b"not finite" in L.kbm_last_error()
+    nanpsf = psf.copy()
+    nanpsf[1, 1] = np.nan
+    assert L.kbm_make_planes(C.byref(st), FAKE, FAKE, None,
+                             nanpsf.ctypes.data_as(C.c_void_p), 3, FAKE, FAKE, None) == 1
+
+
+def _params(vels, **kw):
+    import paper_2109_03296_amd as kbm
+    d = dict(k=4, min_obs=1, sigmag=1, q_lo=0.25, q_hi=0.75, coeff=0.7413,
+             n_sigma=2.0, region=(0, 0, 9, 8))
+    d.update(kw)
+    x0, y0, x1, y1 = d["region"]
+    return kbm._SearchParams(vels.ctypes.data, vels.shape[0], d["k"], d["min_obs"],
+                             d["sigmag"], d["q_lo"], d["q_hi"], d["coeff"],
+                             d["n_sigma"], x0, y0, x1, y1)
+
+
+def test_search_validation_and_workspace_size(L):
+    st, t = _stack()
+    vels = np.array([[1.0, 2.0], [0.0, 0.0], [-3.0, 1.0]], np.float32)
+    nb = C.c_size_t(0)
+    p = _params(vels)
+    assert L.kbm_search_workspace_size(C.byref(st), C.byref(p), 1, C.byref(nb)) == 0
+    # nu plane (T*H*W floats, 256-aligned) + int2 offsets [V][T]
+    nu = 5 * 8 * 9 * 4
+    expect = math.ceil(nu / 256) * 256 + 3 * 5 * 8
+    assert nb.value == math.ceil(expect / 256) * 256
+    for bad in (dict(k=0), dict(k=17), dict(min_obs=0), dict(sigmag=2),
+                dict(q_lo=0.8), dict(q_hi=1.5), dict(coeff=-1.0),
+                dict(n_sigma=float("nan")), dict(region=(0, 0, 10, 8)),
+                dict(region=(5, 0, 4, 8))):
+        pb = _params(vels, **bad)
+        assert L.kbm_search_workspace_size(C.byref(st), C.byref(pb), 1,
+                                           C.byref(nb)) == 1, bad
+    nanv = np.array([[np.nan, 1.0]], np.float32)
+    pn = _params(nanv)
+    assert L.kbm_search_workspace_size(C.byref(st), C.byref(pn), 1, C.byref(nb)) == 1
+    # undersized workspace is reported before anything is enqueued
+    import paper_2109_03296_amd as kbm
+    planes = (C.c_void_p * 1)(0x1000)
+    res = (kbm._Results * 1)(kbm._Results(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, None))
+    rc = L.kbm_search(C.byref(st), planes, planes, C.byref(p), res, 1, FAKE,
+                      C.c_size_t(16), None)
+    assert rc == 5 and b"workspace" in L.kbm_last_error()
+    assert L.kbm_search(C.byref(st), planes, planes, C.byref(p), res, 0, FAKE,
+                        C.c_size_t(1 << 30), None) == 1
+
+
+def test_sigmag_and_refine_validation(L):
+    assert L.kbm_sigmag_filter(FAKE, None, None, 10, 0, 0.25, 0.75, 0.7413, 2.0,
+                               FAKE, None, None) == 1
+    assert L.kbm_sigmag_filter(FAKE, None, None, 10, 65, 0.25, 0.75, 0.7413, 2.0,
+                               FAKE, None, None) == 1
+    assert L.kbm_sigmag_filter(None, None, None, 10, 5, 0.25, 0.75, 0.7413, 2.0,
+                               FAKE, None, None) == 1
+    assert L.kbm_sigmag_filter(FAKE, None, None, 10, 5, 0.75, 0.25, 0.7413, 2.0,
+                               FAKE, None, None) == 1
+    # nothing to do is not an error and touches no device
+    assert L.kbm_sigmag_filter(None, None, None, 0, 5, 0.25, 0.75, 0.7413, 2.0,
+                               None, None, None) == 0
+    st, t = _stack()
+    assert L.kbm_refine(C.byref(st), FAKE, FAKE, -1, FAKE, None, FAKE, None,
+                        None, None, None, None) == 1
+    assert L.kbm_refine(C.byref(st), FAKE, FAKE, 4, FAKE, None, FAKE, FAKE,
+                        None, None, None, None) == 1
+    assert L.kbm_refine(C.byref(st), None, None, 0, None, None, None, None,
+                        None, None, None, None) == 0
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    import paper_2109_03296_amd as kbm
+    x = torch.zeros(2, 4, 4)
+    with pytest.raises(TypeError):
+        kbm.make_planes(x, x, None, np.ones((3, 3), np.float32))

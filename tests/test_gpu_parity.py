@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path (through the C ABI binding) against the FP64
+oracle on the same seeded inputs.
+
+Protocol A: GPU planes vs oracle planes.
+Protocol B: both searches read the oracle's planes rounded to float32, so
+            keep masks must be bit-identical and top-K identical up to near
+            ties.
+Protocol C: each side builds its own planes from the images.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_03296_amd as kbm
+    kbm.lib()
+    return kbm
+
+
+def _cuda(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _oracle_planes32(oracle_mod, st):
+    psi, phi = oracle_mod.planes(st.sci, st.var, st.mask, st.psf)
+    return psi.astype(np.float32), phi.astype(np.float32)
+
+
+def _single_eval(oracle_mod, psi, phi, st, region, p):
+    x0, y0 = region[0], region[1]
+
+    def f(y, x, v):
+        o = oracle_mod.search(psi, phi, st.times, st.vels[v:v + 1], k=1,
+                              region=(x0 + x, y0 + y, x0 + x + 1, y0 + y + 1),
+                              **{k: p[k] for k in ("min_obs", "sigmag", "q_lo",
+                                                   "q_hi", "coeff", "n_sigma")})
+        return float(o["lh"][0, 0, 0])
+    return f
+
+
+# ---------------------------------------------------------------- planes --
+@pytest.mark.parametrize("case", ["c1", "c2crop", "tiny_nan", "c5crop"])
+def test_planes_protocol_A(kbm, oracle_mod, case):
+    _say(f"planes protocol A: {case}")
+    if case == "c1":
+        st = synth.make_config(1)
+    elif case == "c2crop":
+        st = synth.make_config(2, size=(300, 200), n_vel=(4, 4))
+    elif case == "c5crop":
+        st = synth.make_config(5, size=(130, 97), n_vel=(4, 4))
+    else:
+        st = synth.tiny_stack(3, W=37, H=29, T=7, k=5, mask_rate=0.2,
+                              masked_fill=np.nan)
+    psi, phi = kbm.make_planes(_cuda(st.sci), _cuda(st.var), _cuda(st.mask),
+                               st.psf)
+    rpsi, rphi = oracle_mod.planes(st.sci, st.var, st.mask, st.psf)
+    terms = P.plane_terms_abs(oracle_mod, st.sci, st.var, st.mask, st.psf)
+    gpsi, gphi = psi.cpu().numpy(), phi.cpu().numpy()
+    assert np.all(np.abs(gpsi - rpsi) <= 1e-5 * terms + 1e-30)
+    assert np.all(np.abs(gphi - rphi) <= 1e-5 * rphi + 1e-30)
+
+
+def test_planes_masked_fill_bitwise(kbm):
+    a = synth.tiny_stack(4, W=70, H=33, T=5, k=7, mask_rate=0.3)
+    b = synth.tiny_stack(4, W=70, H=33, T=5, k=7, mask_rate=0.3, masked_fill=1e30)
+    pa = kbm.make_planes(_cuda(a.sci), _cuda(a.var), _cuda(a.mask), a.psf)
+    pb = kbm.make_planes(_cuda(b.sci), _cuda(b.var), _cuda(b.mask), b.psf)
+    assert torch.equal(pa[0], pb[0]) and torch.equal(pa[1], pb[1])
+
+
+# ---------------------------------------------------------------- search --
+SEARCH_CASES = {
+    # name: (stack factory, param overrides, region)
+    "c1": (lambda: synth.make_config(1), {}, None),
+    "c2crop_sg": (lambda: synth.make_config(2, size=(300, 200), n_vel=(16, 24)),
+                  {}, None),
+    "c2crop_plain_k16": (lambda: synth.make_config(2, size=(300, 200), n_vel=(12, 12)),
+                         dict(sigmag=0, k=16), (5, 3, 290, 150)),
+    "c5crop": (lambda: synth.make_config(5, size=(160, 128), n_vel=(10, 12)),
+               dict(k=8), None),
+    "tiny_t4": (lambda: synth.tiny_stack(11, W=70, H=9, T=4, n_vel=23), dict(k=5), None),
+    "tiny_t17": (lambda: synth.tiny_stack(12, W=33, H=21, T=17, n_vel=19,
+                                          max_speed=9.0), dict(k=3, min_obs=5), None),
+    "tiny_t40": (lambda: synth.tiny_stack(13, W=65, H=12, T=40, n_vel=9,
+                                          mask_rate=0.3), dict(k=4, min_obs=10), None),
+    "tiny_t64": (lambda: synth.tiny_stack(14, W=20, H=18, T=64, n_vel=7),
+                 dict(k=2, min_obs=1, n_sigma=1.0), None),
+}
+
+
+def _search_both(kbm, oracle_mod, st, over, region, protocol="B"):
+    p = dict(st.params)
+    p.update(over)
+    H, W = st.H, st.W
+    reg = region or (0, 0, W, H)
+    psi, phi = _oracle_planes32(oracle_mod, st)
+    if protocol == "B":
+        gpsi, gphi = _cuda(psi), _cuda(phi)
+    else:
+        gpsi, gphi = kbm.make_planes(_cuda(st.sci), _cuda(st.var),
+                                     _cuda(st.mask), st.psf)
+    sp = kbm.SearchParams(k=p["k"], min_obs=p["min_obs"], sigmag=bool(p["sigmag"]),
+                          q_lo=p["q_lo"], q_hi=p["q_hi"], coeff=p["coeff"],
+                          n_sigma=p["n_sigma"], region=reg)
+    g = kbm.search(gpsi, gphi, st.times, st.vels, sp)
+    torch.cuda.synchronize()
+    r = oracle_mod.search(psi, phi, st.times, st.vels, region=reg, **p)
+    return g, r, psi, phi, p, reg
+
+
+@pytest.mark.parametrize("name", list(SEARCH_CASES))
+def test_search_protocol_B(kbm, oracle_mod, name):
+    make, over, region = SEARCH_CASES[name]
+    st = make()
+    _say(f"search protocol B: {name} T={st.T} H={st.H} W={st.W} V={len(st.vels)}")
+    g, r, psi, phi, p, reg = _search_both(kbm, oracle_mod, st, over, region)
+    stats = P.compare_search(g, r, _single_eval(oracle_mod, psi, phi, st, reg, p))
+    _say(f"  {stats}")
+    gn = P.to_np(g)
+    assert np.any(gn["vel_idx"] >= 0)
+
+
+def test_search_duplicate_velocities_tie_rule(kbm, oracle_mod):
+    st = synth.tiny_stack(15, W=40, H=11, T=6, n_vel=6)
+    st.vels = np.concatenate([st.vels, st.vels[::-1], np.zeros((3, 2), np.float32)])
+    g, r, psi, phi, p, reg = _search_both(kbm, oracle_mod, st, dict(k=8), None)
+    stats = P.compare_search(g, r, None)   # exact ties: identical choices
+    assert stats["tie_swaps"] == 0
+
+
+def test_search_deterministic(kbm, oracle_mod):
+    st = synth.make_config(2, size=(200, 130), n_vel=(8, 8))
+    psi, phi = _oracle_planes32(oracle_mod, st)
+    a = kbm.search(_cuda(psi), _cuda(phi), st.times, st.vels, k=8, min_obs=20)
+    b = kbm.search(_cuda(psi), _cuda(phi), st.times, st.vels, k=8, min_obs=20)
+    for key in a:
+        if a[key] is not None:
+            assert torch.equal(a[key], b[key]), key
+
+
+def test_search_empty_and_all_masked(kbm, oracle_mod):
+    st = synth.tiny_stack(16, W=30, H=10, T=5, n_vel=4)
+    psi = _cuda(np.zeros((5, 10, 30), np.float32))
+    phi = _cuda(np.zeros((5, 10, 30), np.float32))
+    out = kbm.search(psi, phi, st.times, st.vels, k=3)
+    torch.cuda.synchronize()
+    o = P.to_np(out)
+    assert np.all(o["vel_idx"] == -1) and np.all(np.isneginf(o["lh"]))
+    assert np.all(o["keep"] == 0) and np.all(o["n_obs"] == 0)
+    e = kbm.search(psi, phi, st.times, st.vels, k=3, region=(4, 4, 4, 9))
+    assert e["lh"].shape == (5, 0, 3)
+
+
+def test_search_protocol_C(kbm, oracle_mod):
+    """End to end from the images: planes differ by rounding, so keep masks
+    may differ only on decisions within rounding of the threshold."""
+    st = synth.make_config(2, size=(260, 190), n_vel=(12, 16))
+    _say("search protocol C: c2 crop")
+    g, r, psi, phi, p, reg = _search_both(kbm, oracle_mod, st, {}, None, protocol="C")
+    gn = P.to_np(g)
+    same = gn["vel_idx"] == r["vel_idx"]
+    assert same.mean() > 0.99
+    assert np.all(P.lh_close(gn["lh"][same], r["lh"][same]))
+    kd = np.sum(gn["keep"][same] != r["keep"][same].astype(np.uint64))
+    _say(f"  keep-mask differences: {kd} of {same.sum()}")
+    assert kd <= 1e-3 * same.sum() + 2
+
+
+# ---------------------------------------------------------------- sigma_G --
+@pytest.mark.parametrize("T", [1, 2, 5, 26, 33, 60, 64])
+def test_sigmag_filter(kbm, oracle_mod, T):
+    rng = np.random.default_rng(100 + T)
+    n = 3000
+    ps = rng.standard_t(3, size=(n, T)).astype(np.float32)
+    ph = rng.uniform(0.1, 3.0, size=(n, T)).astype(np.float32)
+    valid = (rng.random((n, T)) > 0.15).astype(np.uint8)
+    ph[rng.random((n, T)) < 0.02] = 0.0
+    ps[:50] = 3.25                             # constant lightcurves
+    for phi_given in (True, False):
+        k_g, l_g = kbm.sigmag_filter(_cuda(ps), _cuda(ph) if phi_given else None,
+                                     _cuda(valid))
+        k_r, l_r = oracle_mod.sigmag(ps, ph if phi_given else None, valid)
+        kg = k_g.cpu().numpy().view(np.uint64)
+        assert np.array_equal(kg, k_r)
+        assert np.all(P.lh_close(l_g.cpu().numpy(), l_r))
+
+
+# ---------------------------------------------------------------- refine --
+def _refine_setup(oracle_mod, n=2000, seed=5):
+    st = synth.make_config(2, size=(256, 192), n_vel=(4, 4))
+    psi, phi = _oracle_planes32(oracle_mod, st)
+    rng = np.random.default_rng(seed)
+    params = np.stack([rng.uniform(-5, 260, n), rng.uniform(-5, 195, n),
+                       rng.uniform(-60, 60, n), rng.uniform(-40, 40, n)],
+                      axis=1).astype(np.float32)
+    keep = rng.integers(0, 2 ** 26, size=n).astype(np.uint64)
+    return st, psi, phi, params, keep
+
+
+def test_refine_forward_and_gradient(kbm, oracle_mod):
+    st, psi, phi, params, keep = _refine_setup(oracle_mod)
+    g_up = np.random.default_rng(9).normal(size=len(params)).astype(np.float32)
+    gpsi = torch.zeros(psi.shape, device="cuda")
+    gphi = torch.zeros(phi.shape, device="cuda")
+    lh, gp = kbm.refine_backward(_cuda(psi), _cuda(phi), st.times, _cuda(params),
+                                 _cuda(g_up), _cuda(keep.view(np.int64)),
+                                 gpsi, gphi)
+    rl, rg, rpsi, rphi = oracle_mod.refine(psi, phi, st.times, params, keep,
+                                           grad_lh=g_up.astype(np.float64),
+                                           want_planes=True)
+    assert np.all(P.lh_close(lh.cpu().numpy(), rl))
+    gpn = gp.cpu().numpy().astype(np.float64)
+    num = np.linalg.norm(gpn - rg, axis=1)
+    den = np.linalg.norm(rg, axis=1)
+    big = den > 1e-3 * np.median(den[den > 0])
+    assert np.all(num[big] <= 1e-4 * den[big] + 1e-6)
+    scale = np.abs(rpsi).max()
+    assert np.allclose(gpsi.cpu().numpy(), rpsi, rtol=1e-4, atol=1e-5 * scale)
+    scale = np.abs(rphi).max()
+    assert np.allclose(gphi.cpu().numpy(), rphi, rtol=1e-4, atol=1e-5 * scale)
+    lf = kbm.refine_forward(_cuda(psi), _cuda(phi), st.times, _cuda(params),
+                            _cuda(keep.view(np.int64)))
+    assert torch.equal(lf, lh)
+
+
+def test_refine_fd_fp32_and_autograd(kbm, oracle_mod):
+    st, psi, phi, params, _ = _refine_setup(oracle_mod, n=300, seed=6)
+    P_ = _cuda(params).requires_grad_(True)
+    gpsi_t, gphi_t = _cuda(psi), _cuda(phi)
+    L = kbm.TrajLH.apply(P_, gpsi_t, gphi_t, st.times, None)
+    L.sum().backward()
+    g = P_.grad.cpu().numpy()
+    _, rg = oracle_mod.refine(psi, phi, st.times, params, None,
+                              grad_lh=np.ones(len(params)))
+    den = np.linalg.norm(rg, axis=1)
+    big = den > 1e-3 * np.median(den[den > 0])
+    assert np.all(np.linalg.norm(g - rg, axis=1)[big] <= 1e-4 * den[big] + 1e-6)
+    # fp32 central differences, h = 1e-3 (smoke-level agreement)
+    h = 1e-3
+    fd = np.zeros_like(g)
+    for j in range(4):
+        pp, pm = params.copy(), params.copy()
+        pp[:, j] += h
+        pm[:, j] -= h
+        lp = kbm.refine_forward(gpsi_t, gphi_t, st.times, _cuda(pp)).cpu().numpy()
+        lm = kbm.refine_forward(gpsi_t, gphi_t, st.times, _cuda(pm)).cpu().numpy()
+        fd[:, j] = (lp.astype(np.float64) - lm) / (pp[:, j].astype(np.float64) - pm[:, j])
+    rel = np.linalg.norm(fd - g, axis=1) / np.maximum(np.linalg.norm(g, axis=1), 1e-3)
+    assert np.median(rel) < 1e-2
