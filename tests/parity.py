@@ -31,7 +31,8 @@ def lh_close(a, b, tol=LH_TOL):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     both_inf = np.isneginf(a) & np.isneginf(b)
-    err = np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+    with np.errstate(invalid="ignore"):
+        err = np.abs(a - b) / np.maximum(np.abs(b), 1.0)
     return both_inf | (err <= tol)
 
 
@@ -76,7 +77,8 @@ def _worst(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     fin = np.isfinite(a) & np.isfinite(b)
-    err = np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+    with np.errstate(invalid="ignore"):
+        err = np.abs(a - b) / np.maximum(np.abs(b), 1.0)
     err[~fin] = np.where(a[~fin] == b[~fin], 0, np.inf)
     i = int(np.argmax(err))
     return f"worst at {i}: gpu={a.flat[i]} ref={b.flat[i]} err={err.flat[i]}"

@@ -85,6 +85,14 @@ def test_planes_masked_fill_bitwise(kbm):
 
 
 # ---------------------------------------------------------------- search --
+def _slow(st):
+    """T = 60 over 4 days: a slow grid keeps tracks inside a small crop."""
+    import math
+    st.vels = synth.velocity_grid(np.linspace(0.0, 22.0, 10),
+                                  np.linspace(-math.pi, math.pi, 12, endpoint=False))
+    return st
+
+
 SEARCH_CASES = {
     # name: (stack factory, param overrides, region)
     "c1": (lambda: synth.make_config(1), {}, None),
@@ -92,7 +100,7 @@ SEARCH_CASES = {
                   {}, None),
     "c2crop_plain_k16": (lambda: synth.make_config(2, size=(300, 200), n_vel=(12, 12)),
                          dict(sigmag=0, k=16), (5, 3, 290, 150)),
-    "c5crop": (lambda: synth.make_config(5, size=(160, 128), n_vel=(10, 12)),
+    "c5crop": (lambda: _slow(synth.make_config(5, size=(160, 128), n_vel=(4, 4))),
                dict(k=8), None),
     "tiny_t4": (lambda: synth.tiny_stack(11, W=70, H=9, T=4, n_vel=23), dict(k=5), None),
     "tiny_t17": (lambda: synth.tiny_stack(12, W=33, H=21, T=17, n_vel=19,
