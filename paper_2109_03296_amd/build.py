@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkbm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "planes.hip", "search.hip", "sigmag.hip", "refine.hip"]
+SOURCES = ["api.cpp", "planes.hip", "search.hip", "search_exact_a.hip",
+           "search_exact_b.hip", "sigmag.hip", "refine.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -29,6 +29,8 @@ kbm_status check_stack(const kbm_stack *s, const char *what) {
     KBM_REQUIRE(s->width >= 1 && s->height >= 1, KBM_ERR_INVALID_ARG,
                 "%s: image size %d x %d must be positive", what, s->width,
                 s->height);
+    KBM_REQUIRE(s->width <= (1 << 20) && s->height <= (1 << 20),
+                KBM_ERR_UNSUPPORTED, "%s: image side exceeds 2^20", what);
     KBM_REQUIRE((int64_t)s->width * s->height < (int64_t)1 << 31,
                 KBM_ERR_UNSUPPORTED, "%s: W*H = %lld exceeds 2^31", what,
                 (long long)s->width * s->height);

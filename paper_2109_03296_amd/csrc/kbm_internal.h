@@ -124,38 +124,43 @@ __device__ __forceinline__ float select_rank(const float (&a)[N], int r) {
     return t[0];
 }
 
-// sigma_G keep decision (Section 3.1) for one lightcurve held in registers.
-// nu[i] is psi_i/sqrt(phi_i) for usable epochs and NaN otherwise; n is the
-// number of usable epochs (>= 1).  Binary32 throughout, no contraction:
+// sigma_G cut (Section 3.1) for one lightcurve held in registers.  For
+// epochs i < T, nu[i] is psi_i/sqrt(phi_i) when usable and NaN otherwise;
+// entries i >= T are padding and hold +inf.  r_lo, r_md, r_hi are the
+// nearest ranks of q_lo, 1/2, q_hi for the number of usable epochs.
+// SEL = true when NaN entries may be present (they sort as +inf); with
+// SEL = false every epoch i < T is usable.  Binary32, no contraction:
 //   x_q   = sorted usable nu at rank r_q(n)
 //   sigma = coeff * (x_hi - x_lo);  thr = n_sigma * sigma
 //   keep  = |nu_i - x_md| <= thr   (false for NaN, i.e. unusable epochs)
-// Writes the keep flags into kf[] and returns them as a 64-bit mask.
-template <int N>
-__device__ __forceinline__ uint64_t sigmag_keep(const float (&nu)[N], int n,
-                                                const RankTable &rt,
-                                                float coeff, float n_sigma,
-                                                bool (&kf)[N]) {
+// The caller applies keeps() epoch by epoch (a per-epoch bool array would
+// live in SGPR lane masks and spill).
+struct SigmaGCut {
+    float x_md, thr;
+    __device__ __forceinline__ bool keeps(float nu) const {
 #pragma clang fp contract(off)
-    float s[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) s[i] = (nu[i] == nu[i]) ? nu[i] : INFINITY;
-    sort_network<N>(s);
-    const float x_lo = select_rank<N>(s, rt.lo[n]);
-    const float x_md = select_rank<N>(s, rt.md[n]);
-    const float x_hi = select_rank<N>(s, rt.hi[n]);
-    const float sigma = coeff * (x_hi - x_lo);
-    const float thr = n_sigma * sigma;
-    uint32_t lo = 0, hi = 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        kf[i] = fabsf(nu[i] - x_md) <= thr;
-        if (i < 32)
-            lo |= kf[i] ? (1u << i) : 0u;
-        else
-            hi |= kf[i] ? (1u << (i - 32)) : 0u;
+        return fabsf(nu - x_md) <= thr;
     }
-    return (uint64_t)lo | ((uint64_t)hi << 32);
+};
+
+template <int N, bool SEL>
+__device__ __forceinline__ SigmaGCut sigmag_cut(const float (&nu)[N], int r_lo,
+                                                int r_md, int r_hi,
+                                                float coeff, float n_sigma) {
+#pragma clang fp contract(off)
+    float srt[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        srt[i] = SEL ? ((nu[i] == nu[i]) ? nu[i] : INFINITY) : nu[i];
+    sort_network<N>(srt);
+    const float x_lo = select_rank<N>(srt, r_lo);
+    const float x_md = select_rank<N>(srt, r_md);
+    const float x_hi = select_rank<N>(srt, r_hi);
+    const float sigma = coeff * (x_hi - x_lo);
+    SigmaGCut c;
+    c.x_md = x_md;
+    c.thr = n_sigma * sigma;
+    return c;
 }
 
 }  // namespace kbm

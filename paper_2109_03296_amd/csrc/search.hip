@@ -1,245 +1,97 @@
-// Exhaustive linear-trajectory search with the in-line sigma_G filter and
-// the per-pixel top-K (Section 3, 3.1 and 3.2).
-//
-// Layout and schedule
-//  * The host turns every (velocity, epoch) pair into an integer pixel
-//    offset floor(v t + 1/2) in FP64 once per call ("pointer arithmetic",
-//    Section 3: images are never shifted).  The table is int2 [V][T].
-//  * A prep kernel writes nu = psi / sqrt(phi) (correctly rounded binary32)
-//    for every pixel-epoch into the workspace, or NaN where the pixel is not
-//    usable.  nu depends only on the pixel, so the per-trajectory filter
-//    reads it instead of recomputing a division and a square root per
-//    trajectory-epoch; NaN doubles as the usability flag.
-//  * One wavefront (64 lanes) owns 64 consecutive start pixels of one row
-//    and walks the whole velocity list in order.  For a given velocity all
-//    lanes read 64 consecutive floats per epoch and plane (coalesced), the
-//    offsets are wave-uniform scalar loads, and the lightcurve (psi, phi, nu
-//    for T epochs) lives in VGPRs.  sigma_G runs per lane on that register
-//    copy: a Batcher sorting network and a select tree for the three ranks.
-//  * Each lane keeps its pixel's top-K (L', velocity index) in registers;
-//    the K survivors are re-evaluated once at the end to emit flux, n_obs,
-//    keep bits and the raw likelihood.
-//  * Workgroups are mapped XCD-major: the 8 XCDs each get a contiguous run
-//    of tiles, so the rows a tile needs are shared through one L2.
+// Host side of the trajectory search (Section 3, 3.1, 3.2): argument
+// checks, offset tables, workspace layout, and the launch sequence
+// (tables -> pack prep -> chunked search -> finalize).  Device code and the
+// design notes are in search_kernels.h.
+#include <algorithm>
 #include <vector>
 
-#include "kbm_internal.h"
+#include "search_kernels.h"
 
 namespace kbm {
+namespace srch {
 namespace {
 
-constexpr int WAVE = 64;
-constexpr int NUM_XCD = 8;
+__global__ __launch_bounds__(64) void zero_flags_kernel(int *flags) {
+    if (threadIdx.x == 0) flags[0] = 0;
+}
 
-struct SearchArgs {
-    const float *psi;
-    const float *phi;
-    const float *nu;
-    const int2 *off;  // [V][T] (dx, dy)
-    float *lh;
-    float *flux;
-    int32_t *vidx;
-    int16_t *nobs;
-    uint64_t *keep;
-    float *lh_raw;
-    int W, H, T, V, K, min_obs, sigmag;
-    int x0, y0, Wr, Hr, tiles_x, n_tiles;
-    float coeff, n_sigma;
-    RankTable rt;
-};
-
-__global__ __launch_bounds__(256) void nu_prep_kernel(
+__global__ __launch_bounds__(256) void pack_prep_kernel(
     const float *__restrict__ psi, const float *__restrict__ phi,
-    float *__restrict__ nu, size_t n) {
+    float2 *__restrict__ pk, int *__restrict__ flags, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
+    bool bad = false;
     for (size_t j = i; j < n; j += stride) {
         const float a = psi[j], b = phi[j];
         const bool ok = b > 0.0f && isfinite(b) && isfinite(a);
-        nu[j] = ok ? a / sqrtf(b) : __builtin_nanf("");
+        const float sb = sqrtf(b);
+        pk[j] = ok ? make_float2(a / sb, sb) : make_float2(__builtin_nanf(""), 0.0f);
+        bad |= !ok;
     }
+    if (__any(bad) && (threadIdx.x % WAVE) == 0) atomicOr(flags, 1);
 }
 
-struct TrajOut {
-    float L, Lraw, flux;
-    int nv;
-    uint64_t keep;
-};
-
-__device__ __forceinline__ bool ranks_before(float la, int ia, float lb,
-                                             int ib) {
-    return la > lb || (la == lb && ia < ib);
+// Generic (padded) buckets for epoch counts without an exact variant.
+template <int KM, bool SINGLE>
+void launch_generic_s(const SearchArgs &a, hipStream_t stream) {
+    if (a.T <= 8) launch_chunks<8, KM, false, SINGLE>(a, stream);
+    else if (a.T <= 16) launch_chunks<16, KM, false, SINGLE>(a, stream);
+    else if (a.T <= 24) launch_chunks<24, KM, false, SINGLE>(a, stream);
+    else if (a.T <= 32) launch_chunks<32, KM, false, SINGLE>(a, stream);
+    else if (a.T <= 48) launch_chunks<48, KM, false, SINGLE>(a, stream);
+    else launch_chunks<64, KM, false, SINGLE>(a, stream);
 }
 
-// Evaluate one trajectory: usable epochs, plain sums, optional sigma_G.
+template <int KM>
+void launch_generic(const SearchArgs &a, hipStream_t stream) {
+    if (a.pk_bytes != 0)
+        launch_generic_s<KM, true>(a, stream);
+    else
+        launch_generic_s<KM, false>(a, stream);
+}
+
 template <int TM>
-__device__ __forceinline__ TrajOut eval_traj(const SearchArgs &a, int x,
-                                             int y, const int2 *ov) {
-    float ps[TM], ph[TM], nu[TM];
-    float P = 0.0f, F = 0.0f;
-    int nv = 0;
-    uint32_t vlo = 0, vhi = 0;
-    const size_t HW = (size_t)a.W * a.H;
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        ps[i] = 0.0f;
-        ph[i] = 0.0f;
-        nu[i] = __builtin_nanf("");
-        if (i < a.T) {
-            const int2 o = ov[i];
-            const int xx = x + o.x, yy = y + o.y;
-            if ((unsigned)xx < (unsigned)a.W && (unsigned)yy < (unsigned)a.H) {
-                const size_t q = (size_t)i * HW + (size_t)(yy * a.W + xx);
-                const float c = a.nu[q];
-                const float p = a.psi[q];
-                const float f = a.phi[q];
-                if (c == c) {
-                    ps[i] = p;
-                    ph[i] = f;
-                    nu[i] = c;
-                    ++nv;
-                    P += p;
-                    F += f;
-                    if (i < 32)
-                        vlo |= 1u << i;
-                    else
-                        vhi |= 1u << (i - 32);
-                }
-            }
-        }
-    }
-    TrajOut r;
-    r.nv = nv;
-    r.keep = 0;
-    r.L = -INFINITY;
-    r.Lraw = -INFINITY;
-    r.flux = 0.0f;
-    if (nv == 0) return r;
-    r.Lraw = P / sqrtf(F);
-    if (a.sigmag) {
-        bool kf[TM];
-        r.keep = sigmag_keep<TM>(nu, nv, a.rt, a.coeff, a.n_sigma, kf);
-        float Pk = 0.0f, Fk = 0.0f;
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            Pk += kf[i] ? ps[i] : 0.0f;
-            Fk += kf[i] ? ph[i] : 0.0f;
-        }
-        r.L = Pk / sqrtf(Fk);
-        r.flux = Pk / Fk;
-    } else {
-        r.keep = (uint64_t)vlo | ((uint64_t)vhi << 32);
-        r.L = r.Lraw;
-        r.flux = P / F;
-    }
-    return r;
+void launch_finalize_t(const SearchArgs &a, hipStream_t stream) {
+    const size_t npix = (size_t)a.Wr * a.Hr;
+    const dim3 grid((unsigned)((npix + 255) / 256));
+    if (a.pk_bytes != 0)
+        hipLaunchKernelGGL((finalize_kernel<TM, true>), grid, dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL((finalize_kernel<TM, false>), grid, dim3(256), 0, stream, a);
 }
 
-template <int KM>
-__device__ __forceinline__ int pick_int(const int (&a)[KM], int r) {
-    int v = a[0];
-#pragma unroll
-    for (int j = 1; j < KM; ++j) v = (r == j) ? a[j] : v;
-    return v;
+void launch_finalize(const SearchArgs &a, hipStream_t stream) {
+    if (a.T <= 8) launch_finalize_t<8>(a, stream);
+    else if (a.T <= 16) launch_finalize_t<16>(a, stream);
+    else if (a.T <= 24) launch_finalize_t<24>(a, stream);
+    else if (a.T <= 32) launch_finalize_t<32>(a, stream);
+    else if (a.T <= 48) launch_finalize_t<48>(a, stream);
+    else launch_finalize_t<64>(a, stream);
 }
 
-template <int TM, int KM>
-__global__ __launch_bounds__(WAVE) void search_kernel(SearchArgs a) {
-    // XCD-major tile order: block b runs on XCD b % 8; give each XCD a
-    // contiguous range of tiles.
-    const int b = blockIdx.x;
-    const int q = a.n_tiles / NUM_XCD, rem = a.n_tiles % NUM_XCD;
-    const int xcd = b % NUM_XCD, slot = b / NUM_XCD;
-    const int tile = xcd * q + min(xcd, rem) + slot;
-    const int tx = tile % a.tiles_x, ty = tile / a.tiles_x;
-    const int rx = tx * WAVE + (int)threadIdx.x;
-    const int ry = ty;
-    if (rx >= a.Wr) return;
-    const int x = a.x0 + rx, y = a.y0 + ry;
-
-    float kL[KM];
-    int kI[KM];
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-        // Slots below KM-K are placeholders that rank above everything, so
-        // the K-th best always sits in the last register.
-        const bool ph = j < KM - a.K;
-        kL[j] = ph ? INFINITY : -INFINITY;
-        kI[j] = ph ? -2 : -1;
-    }
-
-    for (int v = 0; v < a.V; ++v) {
-        const TrajOut t = eval_traj<TM>(a, x, y, a.off + (size_t)v * a.T);
-        if (t.nv >= a.min_obs && isfinite(t.L) &&
-            ranks_before(t.L, v, kL[KM - 1], kI[KM - 1])) {
-            kL[KM - 1] = t.L;
-            kI[KM - 1] = v;
-#pragma unroll
-            for (int j = KM - 1; j > 0; --j) {
-                if (ranks_before(kL[j], kI[j], kL[j - 1], kI[j - 1])) {
-                    const float tl = kL[j];
-                    kL[j] = kL[j - 1];
-                    kL[j - 1] = tl;
-                    const int ti = kI[j];
-                    kI[j] = kI[j - 1];
-                    kI[j - 1] = ti;
-                }
-            }
-        }
-    }
-
-    const size_t base = ((size_t)ry * a.Wr + rx) * (size_t)a.K;
-    for (int s = 0; s < a.K; ++s) {
-        const int vi = pick_int<KM>(kI, KM - a.K + s);
-        const size_t o = base + s;
-        if (vi >= 0) {
-            const TrajOut t = eval_traj<TM>(a, x, y, a.off + (size_t)vi * a.T);
-            a.lh[o] = t.L;
-            a.flux[o] = t.flux;
-            a.vidx[o] = vi;
-            a.nobs[o] = (int16_t)t.nv;
-            a.keep[o] = t.keep;
-            if (a.lh_raw) a.lh_raw[o] = t.Lraw;
-        } else {
-            a.lh[o] = -INFINITY;
-            a.flux[o] = 0.0f;
-            a.vidx[o] = -1;
-            a.nobs[o] = 0;
-            a.keep[o] = 0;
-            if (a.lh_raw) a.lh_raw[o] = -INFINITY;
-        }
-    }
-}
-
-template <int TM, int KM>
-void launch_search(const SearchArgs &a, hipStream_t stream) {
-    hipLaunchKernelGGL((search_kernel<TM, KM>), dim3(a.n_tiles), dim3(WAVE), 0,
-                       stream, a);
-}
-
-template <int KM>
-void launch_t(const SearchArgs &a, hipStream_t stream) {
-    if (a.T <= 8) launch_search<8, KM>(a, stream);
-    else if (a.T <= 16) launch_search<16, KM>(a, stream);
-    else if (a.T <= 24) launch_search<24, KM>(a, stream);
-    else if (a.T <= 32) launch_search<32, KM>(a, stream);
-    else if (a.T <= 48) launch_search<48, KM>(a, stream);
-    else launch_search<64, KM>(a, stream);
-}
-
-// Workspace per stack: nu plane, then the offset table.
+// Workspace per stack: packed planes, tables, flags, top-K state.
 struct StackLayout {
-    size_t nu_off, nu_bytes, off_off, off_bytes, end;
+    size_t pk_off, pk_bytes, tab_off, tab_bytes, flags_off, stl_off, sti_off, end;
+    size_t off_rel, lin_rel, box_rel, rank_rel;  // inside the table block
 };
 
 StackLayout layout(const kbm_stack &s, const kbm_search_params &p,
                    size_t start) {
     StackLayout l;
-    l.nu_off = align_up(start, 256);
-    l.nu_bytes = sizeof(float) * (size_t)s.num_epochs * s.width * s.height;
-    l.off_off = align_up(l.nu_off + l.nu_bytes, 256);
-    l.off_bytes = sizeof(int2) * (size_t)p.num_vel * s.num_epochs;
-    l.end = l.off_off + l.off_bytes;
+    const size_t T = s.num_epochs, V = p.num_vel;
+    const size_t npix = (size_t)(p.x_end - p.x_begin) * (p.y_end - p.y_begin);
+    l.pk_off = align_up(start, 256);
+    l.pk_bytes = sizeof(float2) * T * s.width * s.height;
+    l.tab_off = align_up(l.pk_off + l.pk_bytes, 256);
+    l.off_rel = 0;
+    l.lin_rel = align_up(l.off_rel + sizeof(int) * V * T, 16);
+    l.box_rel = align_up(l.lin_rel + sizeof(uint32_t) * V * T, 16);
+    l.rank_rel = align_up(l.box_rel + sizeof(int4) * V, 16);
+    l.tab_bytes = l.rank_rel + sizeof(int) * 3 * 65;
+    l.flags_off = align_up(l.tab_off + l.tab_bytes, 256);
+    l.stl_off = align_up(l.flags_off + 256, 256);
+    l.sti_off = align_up(l.stl_off + sizeof(float) * npix * p.k, 256);
+    l.end = l.sti_off + sizeof(int) * npix * p.k;
     return l;
 }
 
@@ -264,6 +116,12 @@ kbm_status check_search(const kbm_stack *stacks, const kbm_search_params *p,
         kbm_status sg = check_sigmag_params(q.q_lo, q.q_hi, q.coeff, q.n_sigma);
         if (sg != KBM_OK) return sg;
         const kbm_stack &s = stacks[j];
+        KBM_REQUIRE(s.width <= 32767 && s.height <= 32767, KBM_ERR_UNSUPPORTED,
+                    "kbm_search: image sides must be <= 32767 (got %d x %d)",
+                    s.width, s.height);
+        KBM_REQUIRE((uint64_t)s.num_epochs * s.width * s.height < ((uint64_t)1 << 32),
+                    KBM_ERR_UNSUPPORTED,
+                    "kbm_search: T*H*W must be below 2^32 pixel-epochs");
         KBM_REQUIRE(q.x_begin >= 0 && q.x_begin <= q.x_end &&
                         q.x_end <= s.width && q.y_begin >= 0 &&
                         q.y_begin <= q.y_end && q.y_end <= s.height,
@@ -289,28 +147,62 @@ kbm_status check_search(const kbm_stack *stacks, const kbm_search_params *p,
     return KBM_OK;
 }
 
-// floor(v t + 1/2) in FP64, t from the earliest epoch.  This translation
-// unit is compiled with -ffp-contract=off so the product is rounded before
-// the addition.
-void make_offsets(const kbm_stack &s, const kbm_search_params &p,
-                  std::vector<int2> &out) {
-    const int T = s.num_epochs;
+// Offset tables of one stack, laid out as in the workspace table block:
+// (dx, dy) = floor(v t + 1/2) in FP64 with t from the earliest epoch (this
+// translation unit is compiled with -ffp-contract=off, so the product is
+// rounded before the addition), the linear element offset dy*W + dx, and
+// each velocity's offset bounding box.
+// Tables of one stack, laid out as in the workspace table block:
+//  * off16: (dx, dy) = floor(v t + 1/2) in FP64 with t from the earliest
+//    epoch (this translation unit is compiled with -ffp-contract=off, so the
+//    product is rounded before the addition), packed as 16-bit halves;
+//    offsets beyond +/-32767 are clamped, which keeps them out of any image
+//    (sides <= 32767);
+//  * lin: i H W + dy W + dx modulo 2^32, the element offset of epoch i's
+//    sample relative to the start pixel;
+//  * vbox: each velocity's offset bounding box;
+//  * ranks: nearest ranks floor(q (n-1) + 1/2) of q_lo, 1/2, q_hi, n = 0..64.
+void make_tables(const kbm_stack &s, const kbm_search_params &p,
+                 const StackLayout &l, std::vector<char> &buf) {
+    const int T = s.num_epochs, V = p.num_vel;
     double t0 = s.times[0];
     for (int i = 1; i < T; ++i) t0 = std::min(t0, s.times[i]);
-    out.resize((size_t)p.num_vel * T);
-    for (int v = 0; v < p.num_vel; ++v) {
+    buf.assign(l.tab_bytes, 0);
+    int *off = reinterpret_cast<int *>(buf.data() + l.off_rel);
+    uint32_t *lin = reinterpret_cast<uint32_t *>(buf.data() + l.lin_rel);
+    const int64_t HW = (int64_t)s.width * s.height;
+    int4 *box = reinterpret_cast<int4 *>(buf.data() + l.box_rel);
+    int *ranks = reinterpret_cast<int *>(buf.data() + l.rank_rel);
+    for (int v = 0; v < V; ++v) {
         const double vx = (double)p.vel[2 * v], vy = (double)p.vel[2 * v + 1];
+        int4 b = make_int4(INT32_MAX, INT32_MIN, INT32_MAX, INT32_MIN);
         for (int i = 0; i < T; ++i) {
             const double t = s.times[i] - t0;
             const double px = vx * t;
             const double py = vy * t;
-            out[(size_t)v * T + i] =
-                make_int2((int)std::floor(px + 0.5), (int)std::floor(py + 0.5));
+            const int dx = (int)std::floor(px + 0.5), dy = (int)std::floor(py + 0.5);
+            const int cx = std::max(-32767, std::min(32767, dx));
+            const int cy = std::max(-32767, std::min(32767, dy));
+            off[(size_t)v * T + i] = (int)((uint32_t)(cx & 0xffff) | ((uint32_t)cy << 16));
+            const int64_t li = (int64_t)i * HW + (int64_t)cy * s.width + cx;
+            lin[(size_t)v * T + i] = (uint32_t)(uint64_t)li;
+            b.x = std::min(b.x, cx);
+            b.y = std::max(b.y, cx);
+            b.z = std::min(b.z, cy);
+            b.w = std::max(b.w, cy);
         }
+        box[v] = b;
+    }
+    const RankTable rt = make_rank_table(p.q_lo, p.q_hi);
+    for (int n = 0; n <= KBM_MAX_EPOCHS; ++n) {
+        ranks[n] = rt.lo[n];
+        ranks[65 + n] = rt.md[n];
+        ranks[130 + n] = rt.hi[n];
     }
 }
 
 }  // namespace
+}  // namespace srch
 }  // namespace kbm
 
 extern "C" kbm_status kbm_search_workspace_size(const kbm_stack *stacks,
@@ -318,6 +210,7 @@ extern "C" kbm_status kbm_search_workspace_size(const kbm_stack *stacks,
                                                 int32_t num_stacks,
                                                 size_t *bytes) {
     using namespace kbm;
+    using namespace kbm::srch;
     clear_error();
     KBM_REQUIRE(bytes != nullptr, KBM_ERR_INVALID_ARG,
                 "kbm_search_workspace_size: bytes is NULL");
@@ -336,6 +229,7 @@ extern "C" kbm_status kbm_search(const kbm_stack *stacks,
                                  int32_t num_stacks, void *workspace,
                                  size_t workspace_bytes, hipStream_t stream) {
     using namespace kbm;
+    using namespace kbm::srch;
     clear_error();
     kbm_status st = check_search(stacks, p, num_stacks);
     if (st != KBM_OK) return st;
@@ -359,7 +253,7 @@ extern "C" kbm_status kbm_search(const kbm_stack *stacks,
                 workspace_bytes, need);
 
     size_t cursor = 0;
-    std::vector<int2> offs;
+    std::vector<char> tables;
     for (int j = 0; j < num_stacks; ++j) {
         const kbm_stack &s = stacks[j];
         const kbm_search_params &q = p[j];
@@ -368,22 +262,33 @@ extern "C" kbm_status kbm_search(const kbm_stack *stacks,
         const int Wr = q.x_end - q.x_begin, Hr = q.y_end - q.y_begin;
         if (Wr == 0 || Hr == 0) continue;
         char *ws = static_cast<char *>(workspace);
-        float *nu = reinterpret_cast<float *>(ws + l.nu_off);
-        int2 *off = reinterpret_cast<int2 *>(ws + l.off_off);
-        make_offsets(s, q, offs);
-        st = stage_to_device(off, offs.data(), l.off_bytes, stream);
+        make_tables(s, q, l, tables);
+        st = stage_to_device(ws + l.tab_off, tables.data(), l.tab_bytes, stream);
         if (st != KBM_OK) return st;
+        int *flags = reinterpret_cast<int *>(ws + l.flags_off);
+        float2 *pk = reinterpret_cast<float2 *>(ws + l.pk_off);
+        hipLaunchKernelGGL(zero_flags_kernel, dim3(1), dim3(64), 0, stream, flags);
+        KBM_LAUNCHED("zero_flags_kernel");
         const size_t n = (size_t)s.num_epochs * s.width * s.height;
         const int prep_blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
-        hipLaunchKernelGGL(nu_prep_kernel, dim3(prep_blocks), dim3(256), 0,
-                           stream, psi[j], phi[j], nu, n);
-        KBM_LAUNCHED("nu_prep_kernel");
+        hipLaunchKernelGGL(pack_prep_kernel, dim3(prep_blocks), dim3(256), 0,
+                           stream, psi[j], phi[j], pk, flags, n);
+        KBM_LAUNCHED("pack_prep_kernel");
 
         SearchArgs a{};
-        a.psi = psi[j];
-        a.phi = phi[j];
-        a.nu = nu;
-        a.off = off;
+        a.pk = pk;
+        // One buffer descriptor covers every epoch plane when the packed
+        // planes fit 32-bit byte offsets (pk_bytes != 0); larger stacks read
+        // through 64-bit addresses.
+        a.pk_bytes = l.pk_bytes <= 0xffffffffull ? (uint32_t)l.pk_bytes : 0u;
+        a.n_elem = (uint32_t)n;
+        a.off16 = reinterpret_cast<const int *>(ws + l.tab_off + l.off_rel);
+        a.lin = reinterpret_cast<const uint32_t *>(ws + l.tab_off + l.lin_rel);
+        a.vbox = reinterpret_cast<const int4 *>(ws + l.tab_off + l.box_rel);
+        a.ranks = reinterpret_cast<const int *>(ws + l.tab_off + l.rank_rel);
+        a.flags = flags;
+        a.stL = reinterpret_cast<float *>(ws + l.stl_off);
+        a.stI = reinterpret_cast<int *>(ws + l.sti_off);
         a.lh = out[j].lh;
         a.flux = out[j].flux;
         a.vidx = out[j].vel_idx;
@@ -402,15 +307,20 @@ extern "C" kbm_status kbm_search(const kbm_stack *stacks,
         a.Wr = Wr;
         a.Hr = Hr;
         a.tiles_x = (Wr + WAVE - 1) / WAVE;
-        a.n_tiles = a.tiles_x * Hr;
+        const int n_super_x = (a.tiles_x + ST_X - 1) / ST_X;
+        a.n_super_y = (Hr + ST_Y - 1) / ST_Y;
+        a.n_tiles = n_super_x * a.n_super_y * ST_TILES;
         a.coeff = (float)q.coeff;
         a.n_sigma = (float)q.n_sigma;
-        a.rt = make_rank_table(q.q_lo, q.q_hi);
-        if (q.k <= 8)
-            launch_t<8>(a, stream);
-        else
-            launch_t<16>(a, stream);
-        KBM_LAUNCHED("search_kernel");
+        if (!launch_exact_a(a.T, a, stream) && !launch_exact_b(a.T, a, stream)) {
+            if (q.k <= 8)
+                launch_generic<8>(a, stream);
+            else
+                launch_generic<16>(a, stream);
+        }
+        KBM_LAUNCHED("search_chunk_kernel");
+        launch_finalize(a, stream);
+        KBM_LAUNCHED("finalize_kernel");
     }
     return KBM_OK;
 }

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) void sigmag_kernel(
     for (int i = 0; i < TM; ++i) {
         ps[i] = 0.0f;
         ph[i] = 0.0f;
-        nu[i] = __builtin_nanf("");
+        nu[i] = i < T ? __builtin_nanf("") : INFINITY;
         if (i < T) {
             const float a = psi[row + i];
             const float b = phi ? phi[row + i] : 1.0f;
@@ -41,17 +41,23 @@ __global__ __launch_bounds__(256) void sigmag_kernel(
         if (lh) lh[c] = -INFINITY;
         return;
     }
-    bool kf[TM];
-    keep[c] = sigmag_keep<TM>(nu, nv, rt, coeff, n_sigma, kf);
-    if (lh) {
-        float P = 0.0f, F = 0.0f;
+    const SigmaGCut cut = sigmag_cut<TM, true>(nu, rt.lo[nv], rt.md[nv], rt.hi[nv], coeff, n_sigma);
+    float P = 0.0f, F = 0.0f;
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            P += kf[i] ? ps[i] : 0.0f;
-            F += kf[i] ? ph[i] : 0.0f;
+    for (int i = 0; i < TM; ++i) {
+        if (i < T) {
+            const bool k = cut.keeps(nu[i]);
+            P += k ? ps[i] : 0.0f;
+            F += k ? ph[i] : 0.0f;
+            if (i < 32)
+                lo |= k ? (1u << i) : 0u;
+            else
+                hi |= k ? (1u << (i - 32)) : 0u;
         }
-        lh[c] = P / sqrtf(F);
     }
+    keep[c] = (uint64_t)lo | ((uint64_t)hi << 32);
+    if (lh) lh[c] = P / sqrtf(F);
 }
 
 template <int TM>

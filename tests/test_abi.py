@@ -92,10 +92,16 @@ def test_search_validation_and_workspace_size(L):
     nb = C.c_size_t(0)
     p = _params(vels)
     assert L.kbm_search_workspace_size(C.byref(st), C.byref(p), 1, C.byref(nb)) == 0
-    # nu plane (T*H*W floats, 256-aligned) + int2 offsets [V][T]
-    nu = 5 * 8 * 9 * 4
-    expect = math.ceil(nu / 256) * 256 + 3 * 5 * 8
-    assert nb.value == math.ceil(expect / 256) * 256
+    # packed (nu, s) planes, offset tables, flags, top-K state
+    def up(x, a=256):
+        return math.ceil(x / a) * a
+    T, H, W, V, K = 5, 8, 9, 3, 4
+    tab = up(up(up(V * T * 4, 16) + V * T * 4, 16) + V * 16, 16) + 3 * 65 * 4
+    pk = up(T * H * W * 8)
+    flags = up(pk + tab)
+    stl = up(flags + 256)
+    sti = up(stl + 4 * H * W * K)
+    assert nb.value == up(sti + 4 * H * W * K)
     for bad in (dict(k=0), dict(k=17), dict(min_obs=0), dict(sigmag=2),
                 dict(q_lo=0.8), dict(q_hi=1.5), dict(coeff=-1.0),
                 dict(n_sigma=float("nan")), dict(region=(0, 0, 10, 8)),
