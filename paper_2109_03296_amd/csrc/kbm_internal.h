@@ -143,6 +143,24 @@ struct SigmaGCut {
     }
 };
 
+// Same cut with compile-time ranks (no select trees; comparators whose
+// outputs do not reach the three ranks are dead code).
+template <int N, int RL, int RM, int RH>
+__device__ __forceinline__ SigmaGCut sigmag_cut_fixed(const float (&nu)[N],
+                                                      float coeff,
+                                                      float n_sigma) {
+#pragma clang fp contract(off)
+    float srt[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) srt[i] = nu[i];
+    sort_network<N>(srt);
+    const float sigma = coeff * (srt[RH] - srt[RL]);
+    SigmaGCut c;
+    c.x_md = srt[RM];
+    c.thr = n_sigma * sigma;
+    return c;
+}
+
 template <int N, bool SEL>
 __device__ __forceinline__ SigmaGCut sigmag_cut(const float (&nu)[N], int r_lo,
                                                 int r_md, int r_hi,

@@ -72,7 +72,7 @@ void launch_finalize(const SearchArgs &a, hipStream_t stream) {
 // Workspace per stack: packed planes, tables, flags, top-K state.
 struct StackLayout {
     size_t pk_off, pk_bytes, tab_off, tab_bytes, flags_off, stl_off, sti_off, end;
-    size_t off_rel, lin_rel, box_rel, rank_rel;  // inside the table block
+    size_t off_rel, lin_rel, box_rel, mbox_rel, rank_rel;  // in the table block
 };
 
 StackLayout layout(const kbm_stack &s, const kbm_search_params &p,
@@ -86,7 +86,8 @@ StackLayout layout(const kbm_stack &s, const kbm_search_params &p,
     l.off_rel = 0;
     l.lin_rel = align_up(l.off_rel + sizeof(int) * V * T, 16);
     l.box_rel = align_up(l.lin_rel + sizeof(uint32_t) * V * T, 16);
-    l.rank_rel = align_up(l.box_rel + sizeof(int4) * V, 16);
+    l.mbox_rel = align_up(l.box_rel + sizeof(int4) * V, 16);
+    l.rank_rel = align_up(l.mbox_rel + sizeof(int4) * V, 16);
     l.tab_bytes = l.rank_rel + sizeof(int) * 3 * 65;
     l.flags_off = align_up(l.tab_off + l.tab_bytes, 256);
     l.stl_off = align_up(l.flags_off + 256, 256);
@@ -161,6 +162,9 @@ kbm_status check_search(const kbm_stack *stacks, const kbm_search_params *p,
 //  * lin: i H W + dy W + dx modulo 2^32, the element offset of epoch i's
 //    sample relative to the start pixel;
 //  * vbox: each velocity's offset bounding box;
+//  * mbox: the min_obs-th smallest and largest dx and dy of each velocity
+//    (a wave can only reach min_obs usable epochs if, per axis, that many
+//    epochs keep some lane inside the image);
 //  * ranks: nearest ranks floor(q (n-1) + 1/2) of q_lo, 1/2, q_hi, n = 0..64.
 void make_tables(const kbm_stack &s, const kbm_search_params &p,
                  const StackLayout &l, std::vector<char> &buf) {
@@ -172,6 +176,9 @@ void make_tables(const kbm_stack &s, const kbm_search_params &p,
     uint32_t *lin = reinterpret_cast<uint32_t *>(buf.data() + l.lin_rel);
     const int64_t HW = (int64_t)s.width * s.height;
     int4 *box = reinterpret_cast<int4 *>(buf.data() + l.box_rel);
+    int4 *mbox = reinterpret_cast<int4 *>(buf.data() + l.mbox_rel);
+    std::vector<int> sx(T), sy(T);
+    const int m = std::min(p.min_obs, T);
     int *ranks = reinterpret_cast<int *>(buf.data() + l.rank_rel);
     for (int v = 0; v < V; ++v) {
         const double vx = (double)p.vel[2 * v], vy = (double)p.vel[2 * v + 1];
@@ -190,8 +197,16 @@ void make_tables(const kbm_stack &s, const kbm_search_params &p,
             b.y = std::max(b.y, cx);
             b.z = std::min(b.z, cy);
             b.w = std::max(b.w, cy);
+            sx[i] = cx;
+            sy[i] = cy;
         }
         box[v] = b;
+        std::sort(sx.begin(), sx.end());
+        std::sort(sy.begin(), sy.end());
+        if (p.min_obs > T)  // no trajectory can qualify: always skip
+            mbox[v] = make_int4(INT32_MAX / 2, INT32_MIN / 2, INT32_MAX / 2, INT32_MIN / 2);
+        else
+            mbox[v] = make_int4(sx[m - 1], sx[T - m], sy[m - 1], sy[T - m]);
     }
     const RankTable rt = make_rank_table(p.q_lo, p.q_hi);
     for (int n = 0; n <= KBM_MAX_EPOCHS; ++n) {
@@ -285,6 +300,7 @@ extern "C" kbm_status kbm_search(const kbm_stack *stacks,
         a.off16 = reinterpret_cast<const int *>(ws + l.tab_off + l.off_rel);
         a.lin = reinterpret_cast<const uint32_t *>(ws + l.tab_off + l.lin_rel);
         a.vbox = reinterpret_cast<const int4 *>(ws + l.tab_off + l.box_rel);
+        a.mbox = reinterpret_cast<const int4 *>(ws + l.tab_off + l.mbox_rel);
         a.ranks = reinterpret_cast<const int *>(ws + l.tab_off + l.rank_rel);
         a.flags = flags;
         a.stL = reinterpret_cast<float *>(ws + l.stl_off);
@@ -312,6 +328,7 @@ extern "C" kbm_status kbm_search(const kbm_stack *stacks,
         a.n_tiles = n_super_x * a.n_super_y * ST_TILES;
         a.coeff = (float)q.coeff;
         a.n_sigma = (float)q.n_sigma;
+        a.defq = q.q_lo == 0.25 && q.q_hi == 0.75;
         if (!launch_exact_a(a.T, a, stream) && !launch_exact_b(a.T, a, stream)) {
             if (q.k <= 8)
                 launch_generic<8>(a, stream);

@@ -58,6 +58,7 @@ struct SearchArgs {
     const int *off16;         // [V][T] (dx & 0xffff) | (dy << 16)
     const uint32_t *lin;      // [V][T] i H W + dy W + dx (mod 2^32)
     const int4 *vbox;         // [V] (dxmin, dxmax, dymin, dymax)
+    const int4 *mbox;         // [V] min_obs-th smallest/largest dx and dy
     const int *ranks;         // [3][65] quantile ranks by usable count
     const int *flags;         // [0] != 0: some pixel-epoch is unusable
     float *stL;               // [K][Npix] running top-K likelihoods
@@ -72,6 +73,7 @@ struct SearchArgs {
     int x0, y0, Wr, Hr, tiles_x, n_super_y, n_tiles;
     int v_begin, v_end, first;
     float coeff, n_sigma;
+    int defq;                 // quantiles are (0.25, 0.75): fixed ranks
 };
 
 __device__ __forceinline__ bool ranks_before(float la, int ia, float lb,
@@ -149,6 +151,33 @@ __device__ __forceinline__ Score score(const SearchArgs &a,
     r.L = P / sqrtf(F);
     r.flux = P / F;
     return r;
+}
+
+// Clean, exact-T fast path with the default quantiles (0.25, 0.75): every
+// epoch is usable, the nearest ranks floor(q (T-1) + 1/2) are compile-time
+// constants, and the kept sums zero s instead of selecting twice.
+template <int T>
+__device__ __forceinline__ float score_fixed(const SearchArgs &a,
+                                             const float (&nu)[T],
+                                             const float (&s)[T]) {
+    constexpr int RL = (T + 1) / 4, RM = T / 2, RH = (3 * T - 1) / 4;
+    float P = 0.0f, F = 0.0f;
+    if (a.sigmag) {
+        const SigmaGCut c = sigmag_cut_fixed<T, RL, RM, RH>(nu, a.coeff, a.n_sigma);
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const float sk = c.keeps(nu[i]) ? s[i] : 0.0f;
+            P = fmaf(nu[i], sk, P);
+            F = fmaf(sk, sk, F);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            P = fmaf(nu[i], s[i], P);
+            F = fmaf(s[i], s[i], F);
+        }
+    }
+    return P / sqrtf(F);
 }
 
 // Whole-wave in-bounds load: the per-epoch offset is wave-uniform.
@@ -259,13 +288,24 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
         const bool fast = xw + bx.x >= 0 &&
                           xw + (WAVE - 1) + bx.y < a.W && y + bx.z >= 0 &&
                           y + bx.w < a.H;
+        if (!fast) {
+            // Sound skip: if fewer than min_obs epochs can hold any lane of
+            // this wave in the image (per axis), no lane reaches min_obs.
+            const int4 mb = a.mbox[v];
+            if (xw + mb.x > a.W - 1 || xw + (WAVE - 1) + mb.y < 0 ||
+                y + mb.z > a.H - 1 || y + mb.w < 0)
+                continue;
+        }
         float nu[TM], s[TM];
         int nv;
         Score sc;
         if (fast) {
             nv = load_fast<TM, CLEAN, EXACT, SINGLE>(a, rs, lane, wave_e,
                                                      a.lin + (size_t)v * T, nu, s);
-            sc = score<TM, !CLEAN, EXACT>(a, nu, s, nv);
+            if (EXACT && CLEAN && a.defq)
+                sc.L = score_fixed<TM>(a, nu, s);
+            else
+                sc = score<TM, !CLEAN, EXACT>(a, nu, s, nv);
         } else {
             nv = load_slow<TM, EXACT, SINGLE>(a, rs, x, y, a.off16 + (size_t)v * T,
                                               a.lin + (size_t)v * T, nu, s);

@@ -96,7 +96,7 @@ def test_search_validation_and_workspace_size(L):
     def up(x, a=256):
         return math.ceil(x / a) * a
     T, H, W, V, K = 5, 8, 9, 3, 4
-    tab = up(up(up(V * T * 4, 16) + V * T * 4, 16) + V * 16, 16) + 3 * 65 * 4
+    tab = up(up(up(up(V * T * 4, 16) + V * T * 4, 16) + V * 16, 16) + V * 16, 16) + 3 * 65 * 4
     pk = up(T * H * W * 8)
     flags = up(pk + tab)
     stl = up(flags + 256)
