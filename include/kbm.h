@@ -190,6 +190,53 @@ kbm_status kbm_refine(const kbm_stack *s, const float *psi, const float *phi,
                       float *lh, const float *grad_lh, float *grad_params,
                       float *grad_psi, float *grad_phi, hipStream_t stream);
 
+/*
+ * kbm_extract_top - candidate extraction: the global top-N result slots by
+ * filtered likelihood with L' >= lh_min (the paper hands trajectories whose
+ * recomputed likelihood clears a threshold on from the GPU, Section 3.1, and
+ * keeps per-pixel lists, Section 3.2; this collects them across pixels).
+ *
+ * Slots are ranked by L' descending, then by flat slot index
+ * ((y - y_begin) * Wr + (x - x_begin)) * k + slot ascending; empty and
+ * non-finite slots never qualify.  The first min(n_max, #qualifying) are
+ * written in increasing flat index order.
+ *
+ *   r         : device results of kbm_search, [Hr][Wr][k]
+ *   vel       : host [num_vel][2], the velocity list the search used
+ *   params    : device float [n_max][4] out: (x, y, vx, vy) of each slot
+ *   lh        : device float [n_max] out
+ *   flux, keep, index (int64 flat slot index), n_obs : device, may be NULL
+ *   n_out     : device int64 [1], number written
+ *   workspace : device, >= kbm_extract_workspace_size bytes
+ * Hr*Wr*k must be below 2^32.
+ */
+kbm_status kbm_extract_workspace_size(int32_t Hr, int32_t Wr, int32_t k,
+                                      int32_t num_vel, size_t *bytes);
+kbm_status kbm_extract_top(const kbm_results *r, int32_t Hr, int32_t Wr,
+                           int32_t k, int32_t x_begin, int32_t y_begin,
+                           const float *vel, int32_t num_vel, float lh_min,
+                           int64_t n_max, float *params, float *lh, float *flux,
+                           uint64_t *keep, int64_t *index, int16_t *n_obs,
+                           int64_t *n_out, void *workspace,
+                           size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * kbm_adam_step - one Adam update (Kingma & Ba 2015, Algorithm 1) of the
+ * refinement parameters, the optimiser that drives kbm_refine's gradient
+ * ascent.  With g the gradient (negated when maximize != 0):
+ *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2
+ *   p <- p - lr[c] * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps)
+ * where c is the column of the element (row-major [n][cols]).
+ *
+ *   params, m, v : device float [n][cols], updated in place
+ *   grad         : device float [n][cols]
+ *   lr           : host float [cols]; cols in [1, 8]; step >= 1
+ */
+kbm_status kbm_adam_step(float *params, const float *grad, float *m, float *v,
+                         int64_t n, int32_t cols, const float *lr,
+                         double beta1, double beta2, double eps, int32_t step,
+                         int32_t maximize, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -179,3 +179,29 @@ def refine(psi, phi, times, params, keep=None, grad_lh=None, want_planes=False):
     if want_planes:
         return lh, gp, gpsi, gphi
     return lh, gp
+
+
+def extract_top(lh, n_max, lh_min=-np.inf):
+    """Global top-N slots of a search result ``lh`` [Hr][Wr][K] (plain
+    definition): qualifying slots are finite with L' >= lh_min; rank by L'
+    descending then flat slot index ascending; keep the first n_max; return
+    their flat indices in increasing order."""
+    flat = np.asarray(lh, np.float64).ravel()
+    idx = np.arange(flat.size)
+    ok = np.isfinite(flat) & (flat >= lh_min)
+    order = np.lexsort((idx[ok], -flat[ok]))
+    return np.sort(idx[ok][order][:n_max])
+
+
+def adam_step(p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8,
+              maximize=True):
+    """One Adam update (Kingma & Ba, Algorithm 1) in FP64, per-column lr.
+    Returns new (p, m, v)."""
+    p, g, m, v = (np.asarray(a, np.float64) for a in (p, g, m, v))
+    g = -g if maximize else g
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** step)
+    vh = v / (1.0 - beta2 ** step)
+    p = p - np.asarray(lr, np.float64) * mh / (np.sqrt(vh) + eps)
+    return p, m, v

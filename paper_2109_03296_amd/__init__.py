@@ -26,7 +26,7 @@ __all__ = [
     "KbmError", "lib", "make_planes", "search", "search_batched",
     "search_workspace_size", "sigmag_filter", "refine_forward",
     "refine_backward", "TrajLH", "SearchParams", "MAX_EPOCHS", "MAX_K",
-    "MAX_PSF",
+    "MAX_PSF", "extract_top", "adam_step", "refine",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -86,6 +86,12 @@ def lib():
         L.kbm_sigmag_filter.argtypes = [P, P, P, i64, i32, f64, f64, f64, f64,
                                         P, P, P]
         L.kbm_refine.argtypes = [P, P, P, i64, P, P, P, P, P, P, P, P]
+        L.kbm_extract_workspace_size.argtypes = [i32, i32, i32, i32, P]
+        L.kbm_extract_top.argtypes = [P, i32, i32, i32, i32, i32, P, i32,
+                                      C.c_float, i64, P, P, P, P, P, P, P, P,
+                                      C.c_size_t, P]
+        L.kbm_adam_step.argtypes = [P, P, P, P, i64, i32, P, f64, f64, f64,
+                                    i32, i32, P]
         _lib = L
         return L
 
@@ -341,3 +347,77 @@ class TrajLH(torch.autograd.Function):
         _, gp = refine_backward(psi, phi, ctx.times, params,
                                 grad_lh.contiguous().float(), keep, gpsi, gphi)
         return gp, gpsi, gphi, None, None
+
+
+def extract_top(res, vels, n_max, lh_min=-float("inf"), region_origin=(0, 0),
+                workspace=None, stream=None):
+    """Global top-``n_max`` result slots of a search by L' (>= lh_min).
+
+    Returns a dict of device tensors (params [n][4] = x, y, vx, vy; lh; flux;
+    keep; index; n_obs) trimmed to the number found, in flat-slot order."""
+    lh_t = _dev(res["lh"], torch.float32, "lh")
+    Hr, Wr, k = lh_t.shape
+    dev = lh_t.device
+    vels = _host(vels, np.float32).reshape(-1, 2)
+    r = _Results(res["lh"].data_ptr(), res["flux"].data_ptr(),
+                 res["vel_idx"].data_ptr(), res["n_obs"].data_ptr(),
+                 res["keep"].data_ptr(), None)
+    L = lib()
+    nb = C.c_size_t(0)
+    _check("kbm_extract_workspace_size",
+           L.kbm_extract_workspace_size(Hr, Wr, k, vels.shape[0], C.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=dev)
+    n_max = int(n_max)
+    out = dict(params=torch.empty((max(n_max, 1), 4), dtype=torch.float32, device=dev),
+               lh=torch.empty(max(n_max, 1), dtype=torch.float32, device=dev),
+               flux=torch.empty(max(n_max, 1), dtype=torch.float32, device=dev),
+               keep=torch.empty(max(n_max, 1), dtype=torch.int64, device=dev),
+               index=torch.empty(max(n_max, 1), dtype=torch.int64, device=dev),
+               n_obs=torch.empty(max(n_max, 1), dtype=torch.int16, device=dev))
+    n_out = torch.zeros(1, dtype=torch.int64, device=dev)
+    _check("kbm_extract_top", L.kbm_extract_top(
+        C.byref(r), Hr, Wr, k, int(region_origin[0]), int(region_origin[1]),
+        vels.ctypes.data_as(C.c_void_p), vels.shape[0], float(lh_min), n_max,
+        _ptr(out["params"]), _ptr(out["lh"]), _ptr(out["flux"]), _ptr(out["keep"]),
+        _ptr(out["index"]), _ptr(out["n_obs"]), _ptr(n_out), _ptr(workspace),
+        workspace.numel(), _stream(stream)))
+    n = int(n_out.item())
+    return {key: v[:n] for key, v in out.items()}
+
+
+def adam_step(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8,
+              maximize=True, stream=None):
+    """One in-place Adam update of ``params`` [n][cols] (per-column lr)."""
+    for t, nm in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _dev(t, torch.float32, nm, params.shape)
+    n, cols = params.shape
+    lr = np.ascontiguousarray(np.broadcast_to(np.asarray(lr, np.float32), (cols,)))
+    _check("kbm_adam_step", lib().kbm_adam_step(
+        _ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, cols,
+        lr.ctypes.data_as(C.c_void_p), beta1, beta2, eps, int(step),
+        int(bool(maximize)), _stream(stream)))
+
+
+def refine(psi, phi, times, params0, keep=None, steps=50, lr_pos=0.3,
+           lr_vel=None, cosine=True, stream=None):
+    """Gradient-ascent refinement of candidates with the bilinear adjoint.
+
+    Each step runs the adjoint kernel (L and dL/dparams) and one Adam update
+    kernel.  Position steps are ``lr_pos`` pixels; velocity steps default to
+    ``lr_pos / t_span`` px/day so that both move the track by similar
+    amounts.  A cosine decay scales both.  Returns (params, lh) where lh is
+    the likelihood at the returned params."""
+    t = np.asarray(times, np.float64)
+    span = float(t.max() - t.min()) or 1.0
+    lr_vel = lr_pos / span if lr_vel is None else lr_vel
+    p = params0.detach().clone().contiguous()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    ones = torch.ones(p.shape[0], dtype=torch.float32, device=p.device)
+    for it in range(1, steps + 1):
+        scale = 0.5 * (1.0 + np.cos(np.pi * (it - 1) / steps)) if cosine else 1.0
+        _, g = refine_backward(psi, phi, times, p, ones, keep, stream=stream)
+        adam_step(p, g, m, v, [lr_pos * scale, lr_pos * scale, lr_vel * scale,
+                               lr_vel * scale], it, maximize=True, stream=stream)
+    return p, refine_forward(psi, phi, times, p, keep, stream=stream)

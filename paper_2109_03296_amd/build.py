@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkbm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.cpp", "planes.hip", "search.hip", "search_exact_a.hip",
-           "search_exact_b.hip", "sigmag.hip", "refine.hip"]
+           "search_exact_b.hip", "sigmag.hip", "refine.hip", "extract.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -32,8 +32,8 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, extra=()) -> str:
-    obj = os.path.join(BUILD_DIR, src + ".o")
+def _compile(src: str, extra=(), build_dir=None) -> str:
+    obj = os.path.join(build_dir or BUILD_DIR, src + ".o")
     cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src),
            "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,18 +47,20 @@ def _compile(src: str, extra=()) -> str:
     return obj
 
 
-def build(extra_flags=(), jobs: int = 8) -> str:
-    """Compile all sources and link libkbm.so; returns the library path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(extra_flags=(), jobs: int = 8, lib=None, build_dir=None) -> str:
+    """Compile all sources and link libkbm.so (or ``lib``); returns its path."""
+    lib = lib or LIB
+    build_dir = build_dir or BUILD_DIR
+    os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra_flags), SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda s: _compile(s, extra_flags, build_dir), SOURCES))
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -183,3 +183,78 @@ extern "C" kbm_status kbm_refine(const kbm_stack *s, const float *psi,
     KBM_LAUNCHED("refine_kernel");
     return KBM_OK;
 }
+
+// ---------------------------------------------------------------------
+// Adam update of the refinement parameters (Kingma & Ba, Algorithm 1):
+// m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2, p -= lr_col * mhat/(sqrt(vhat)+eps)
+// with mhat = m/(1-b1^t), vhat = v/(1-b2^t); maximize flips the sign of g.
+// ---------------------------------------------------------------------
+namespace kbm {
+namespace {
+
+constexpr int ADAM_MAX_COLS = 8;
+
+struct AdamArgs {
+    float *p;
+    const float *g;
+    float *m;
+    float *v;
+    int64_t n;  // elements
+    int cols;
+    float lr[ADAM_MAX_COLS];
+    float b1, b2, eps, c1, c2, sign;
+};
+
+__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const float g = a.sign * a.g[i];
+    const float m = a.b1 * a.m[i] + (1.0f - a.b1) * g;
+    const float v = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
+    a.m[i] = m;
+    a.v[i] = v;
+    const float mh = m / a.c1, vh = v / a.c2;
+    a.p[i] -= a.lr[i % a.cols] * mh / (sqrtf(vh) + a.eps);
+}
+
+}  // namespace
+}  // namespace kbm
+
+extern "C" kbm_status kbm_adam_step(float *params, const float *grad, float *m,
+                                    float *v, int64_t n, int32_t cols,
+                                    const float *lr, double beta1, double beta2,
+                                    double eps, int32_t step, int32_t maximize,
+                                    hipStream_t stream) {
+    using namespace kbm;
+    clear_error();
+    KBM_REQUIRE(n >= 0 && cols >= 1 && cols <= ADAM_MAX_COLS && lr != nullptr,
+                KBM_ERR_INVALID_ARG, "kbm_adam_step: bad shape (n=%lld, cols=%d)",
+                (long long)n, cols);
+    KBM_REQUIRE(n == 0 || (params && grad && m && v), KBM_ERR_INVALID_ARG,
+                "kbm_adam_step: arrays must be non-NULL");
+    KBM_REQUIRE(step >= 1, KBM_ERR_INVALID_ARG, "kbm_adam_step: step must be >= 1");
+    KBM_REQUIRE(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0,
+                KBM_ERR_INVALID_ARG, "kbm_adam_step: bad betas or eps");
+    for (int c = 0; c < cols; ++c)
+        KBM_REQUIRE(std::isfinite(lr[c]), KBM_ERR_INVALID_ARG, "kbm_adam_step: lr not finite");
+    const int64_t total = n * cols;
+    if (total == 0) return KBM_OK;
+    AdamArgs a{};
+    a.p = params;
+    a.g = grad;
+    a.m = m;
+    a.v = v;
+    a.n = total;
+    a.cols = cols;
+    for (int c = 0; c < cols; ++c) a.lr[c] = lr[c];
+    a.b1 = (float)beta1;
+    a.b2 = (float)beta2;
+    a.eps = (float)eps;
+    a.c1 = (float)(1.0 - std::pow(beta1, (double)step));
+    a.c2 = (float)(1.0 - std::pow(beta2, (double)step));
+    a.sign = maximize ? -1.0f : 1.0f;
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       stream, a);
+    KBM_LAUNCHED("adam_kernel");
+    return KBM_OK;
+}

@@ -43,12 +43,35 @@
 namespace kbm {
 namespace srch {
 
+#ifndef KBM_ST_X
+#define KBM_ST_X 4
+#endif
+#ifndef KBM_ST_Y
+#define KBM_ST_Y 16
+#endif
+#ifndef KBM_VCHUNK
+#define KBM_VCHUNK 256
+#endif
+#ifndef KBM_MAX_WAVES_PER_SIMD
+#define KBM_MAX_WAVES_PER_SIMD 8
+#endif
+#ifndef KBM_STAGGER
+#define KBM_STAGGER 1
+#endif
+#ifndef KBM_PIPE
+#define KBM_PIPE 0
+#endif
+#ifndef KBM_NW
+#define KBM_NW 1
+#endif
+
 constexpr int WAVE = 64;
 constexpr int NUM_XCD = 8;
-constexpr int ST_X = 4;     // tiles (of 64 px) across a super-tile
-constexpr int ST_Y = 16;    // rows in a super-tile
+constexpr int ST_X = KBM_ST_X;      // tiles (of 64 px) across a super-tile
+constexpr int ST_Y = KBM_ST_Y;      // rows in a super-tile
 constexpr int ST_TILES = ST_X * ST_Y;
-constexpr int VCHUNK = 256; // velocities per launch
+constexpr int VCHUNK = KBM_VCHUNK;  // velocities per launch
+constexpr int NW = KBM_NW;          // waves per workgroup sharing a tile
 constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer descriptor, CDNA
 
 struct SearchArgs {
@@ -253,7 +276,12 @@ __device__ __forceinline__ bool map_tile(const SearchArgs &a, int &tx, int &ty) 
 
 template <int TM, int KM, bool CLEAN, bool EXACT, bool SINGLE>
 __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
-    const unsigned lane = threadIdx.x;
+    // NW waves share this tile's 64 start pixels and interleave the chunk's
+    // velocities (wave w takes v = v_begin + w, w + NW, ...), so at any time
+    // they read nearly the same plane rows: lines are shared through L1 and
+    // the per-XCD footprint of a velocity step shrinks NW-fold.
+    const unsigned lane = threadIdx.x % WAVE;
+    const int w = NW > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)) : 0;
     const int rx = tx * WAVE + (int)lane, ry = ty;
     const bool active = rx < a.Wr;
     const int xw = a.x0 + tx * WAVE;
@@ -273,7 +301,7 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
         if (slot < 0) {
             kL[j] = INFINITY;
             kI[j] = -2;
-        } else if (a.first || !active) {
+        } else if (a.first || !active || w != 0) {
             kL[j] = -INFINITY;
             kI[j] = -1;
         } else {
@@ -283,7 +311,11 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
     }
 
     const uint32_t wave_e = (uint32_t)(y * a.W + xw);
-    for (int v = a.v_begin; v < a.v_end; ++v) {
+    const int nvel = a.v_end - a.v_begin;
+    const int rot = KBM_STAGGER > 1 ? (int)((blockIdx.x / NUM_XCD) % KBM_STAGGER) * nvel / KBM_STAGGER : 0;
+    for (int vv = w; vv < nvel; vv += NW) {
+        int v = a.v_begin + vv + rot;
+        if (v >= a.v_end) v -= nvel;
         const int4 bx = a.vbox[v];
         const bool fast = xw + bx.x >= 0 &&
                           xw + (WAVE - 1) + bx.y < a.W && y + bx.z >= 0 &&
@@ -328,6 +360,168 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
             }
         }
     }
+    if (NW > 1) {
+        // Merge the waves' lists into wave 0's through LDS.  The ranking
+        // compares velocity indices on ties, so the merge order is immaterial.
+        __shared__ float mL[NW > 1 ? NW - 1 : 1][KM][WAVE];
+        __shared__ int mI[NW > 1 ? NW - 1 : 1][KM][WAVE];
+        if (w > 0) {
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                mL[w - 1][j][lane] = kL[j];
+                mI[w - 1][j][lane] = kI[j];
+            }
+        }
+        __syncthreads();
+        if (w != 0) return;
+        for (int o = 0; o < NW - 1; ++o) {
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                const float L = mL[o][j][lane];
+                const int v = mI[o][j][lane];
+                if (v >= 0 && ranks_before(L, v, kL[KM - 1], kI[KM - 1])) {
+                    kL[KM - 1] = L;
+                    kI[KM - 1] = v;
+#pragma unroll
+                    for (int jj = KM - 1; jj > 0; --jj) {
+                        if (ranks_before(kL[jj], kI[jj], kL[jj - 1], kI[jj - 1])) {
+                            const float tl = kL[jj];
+                            kL[jj] = kL[jj - 1];
+                            kL[jj - 1] = tl;
+                            const int ti = kI[jj];
+                            kI[jj] = kI[jj - 1];
+                            kI[jj - 1] = ti;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (!active) return;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        const int slot = j - (KM - a.K);
+        if (slot >= 0) {
+            a.stL[(size_t)slot * npix + pix] = kL[j];
+            a.stI[(size_t)slot * npix + pix] = kI[j];
+        }
+    }
+}
+
+// Insert (L, v) into a lane's sorted top-K registers.
+template <int KM>
+__device__ __forceinline__ void topk_insert(float (&kL)[KM], int (&kI)[KM],
+                                            float L, int v) {
+    kL[KM - 1] = L;
+    kI[KM - 1] = v;
+#pragma unroll
+    for (int j = KM - 1; j > 0; --j) {
+        if (ranks_before(kL[j], kI[j], kL[j - 1], kI[j - 1])) {
+            const float tl = kL[j];
+            kL[j] = kL[j - 1];
+            kL[j - 1] = tl;
+            const int ti = kI[j];
+            kI[j] = kI[j - 1];
+            kI[j - 1] = ti;
+        }
+    }
+}
+
+// One velocity of the software-pipelined sweep (clean stacks, exact T,
+// single buffer).  cur holds this velocity's samples when it is on the fast
+// path (loaded one step earlier); the next velocity's loads are issued into
+// nxt before this velocity is scored, so they travel while the lane sorts.
+template <int T, int KM>
+__device__ __forceinline__ void pipe_step(const SearchArgs &a,
+                                          __amdgpu_buffer_rsrc_t rs,
+                                          unsigned lane, int x, int y, int xw,
+                                          uint32_t wave_e, bool active, int v,
+                                          bool fast_v, int vn, bool fast_n,
+                                          float (&cn)[T], float (&cs)[T],
+                                          float (&nn)[T], float (&ns)[T],
+                                          float (&kL)[KM], int (&kI)[KM]) {
+    if (fast_n)
+        load_fast<T, true, true, true>(a, rs, lane, wave_e, a.lin + (size_t)vn * T, nn, ns);
+    float L;
+    int nv = T;
+    if (fast_v) {
+        if (a.defq) {
+            L = score_fixed<T>(a, cn, cs);
+        } else {
+            L = score<T, false, true>(a, cn, cs, T).L;
+        }
+    } else {
+        const int4 mb = a.mbox[v];
+        if (xw + mb.x > a.W - 1 || xw + (WAVE - 1) + mb.y < 0 ||
+            y + mb.z > a.H - 1 || y + mb.w < 0)
+            return;
+        nv = load_slow<T, true, true>(a, rs, x, y, a.off16 + (size_t)v * T,
+                                      a.lin + (size_t)v * T, cn, cs);
+        L = score<T, true, true>(a, cn, cs, nv).L;
+    }
+    if (active && nv >= a.min_obs && isfinite(L) &&
+        ranks_before(L, v, kL[KM - 1], kI[KM - 1]))
+        topk_insert<KM>(kL, kI, L, v);
+}
+
+template <int T, int KM>
+__device__ __forceinline__ void run_chunk_pipe(const SearchArgs &a, int tx, int ty) {
+    const unsigned lane = threadIdx.x;
+    const int rx = tx * WAVE + (int)lane, ry = ty;
+    const bool active = rx < a.Wr;
+    const int xw = a.x0 + tx * WAVE;
+    const int x = xw + (int)lane, y = a.y0 + ry;
+    const size_t npix = (size_t)a.Wr * a.Hr;
+    const size_t pix = (size_t)ry * a.Wr + (active ? rx : 0);
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a);
+
+    float kL[KM];
+    int kI[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        const int slot = j - (KM - a.K);
+        if (slot < 0) {
+            kL[j] = INFINITY;
+            kI[j] = -2;
+        } else if (a.first || !active) {
+            kL[j] = -INFINITY;
+            kI[j] = -1;
+        } else {
+            kL[j] = a.stL[(size_t)slot * npix + pix];
+            kI[j] = a.stI[(size_t)slot * npix + pix];
+        }
+    }
+    const uint32_t wave_e = (uint32_t)(y * a.W + xw);
+    const int nvel = a.v_end - a.v_begin;
+    const int rot = KBM_STAGGER > 1 ? (int)((blockIdx.x / NUM_XCD) % KBM_STAGGER) * nvel / KBM_STAGGER : 0;
+    auto vel_at = [&](int vv) {
+        int v = a.v_begin + vv + rot;
+        return v >= a.v_end ? v - nvel : v;
+    };
+    auto is_fast = [&](int v) {
+        const int4 bx = a.vbox[v];
+        return xw + bx.x >= 0 && xw + (WAVE - 1) + bx.y < a.W && y + bx.z >= 0 &&
+               y + bx.w < a.H;
+    };
+    float An[T], As[T], Bn[T], Bs[T];
+    int v = vel_at(0);
+    bool fv = is_fast(v);
+    if (fv) load_fast<T, true, true, true>(a, rs, lane, wave_e, a.lin + (size_t)v * T, An, As);
+    for (int vv = 0; vv < nvel; vv += 2) {
+        const bool has1 = vv + 1 < nvel;
+        const int v1 = has1 ? vel_at(vv + 1) : v;
+        const bool f1 = has1 && is_fast(v1);
+        pipe_step<T, KM>(a, rs, lane, x, y, xw, wave_e, active, v, fv, v1, f1,
+                         An, As, Bn, Bs, kL, kI);
+        if (!has1) break;
+        const bool has2 = vv + 2 < nvel;
+        const int v2 = has2 ? vel_at(vv + 2) : v1;
+        const bool f2 = has2 && is_fast(v2);
+        pipe_step<T, KM>(a, rs, lane, x, y, xw, wave_e, active, v1, f1, v2, f2,
+                         Bn, Bs, An, As, kL, kI);
+        v = v2;
+        fv = f2;
+    }
     if (!active) return;
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
@@ -340,13 +534,19 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
 }
 
 template <int TM, int KM, bool EXACT, bool SINGLE>
-__global__ __launch_bounds__(WAVE) void search_chunk_kernel(SearchArgs a) {
+__global__ __launch_bounds__(WAVE * NW)
+__attribute__((amdgpu_waves_per_eu(1, KBM_MAX_WAVES_PER_SIMD)))
+void search_chunk_kernel(SearchArgs a) {
     int tx, ty;
     if (!map_tile(a, tx, ty)) return;
-    if (a.flags[0] == 0)
-        run_chunk<TM, KM, true, EXACT, SINGLE>(a, tx, ty);
-    else
+    if (a.flags[0] == 0) {
+        if (KBM_PIPE && NW == 1 && EXACT && SINGLE)
+            run_chunk_pipe<TM, KM>(a, tx, ty);
+        else
+            run_chunk<TM, KM, true, EXACT, SINGLE>(a, tx, ty);
+    } else {
         run_chunk<TM, KM, false, EXACT, SINGLE>(a, tx, ty);
+    }
 }
 
 // Re-evaluate each pixel's K winners and write all result fields.
@@ -401,7 +601,7 @@ void launch_chunks(SearchArgs a, hipStream_t stream) {
         a.v_end = v0 + VCHUNK < a.V ? v0 + VCHUNK : a.V;
         a.first = v0 == 0;
         hipLaunchKernelGGL((search_chunk_kernel<TM, KM, EXACT, SINGLE>), dim3(a.n_tiles),
-                           dim3(WAVE), 0, stream, a);
+                           dim3(WAVE * NW), 0, stream, a);
     }
 }
 

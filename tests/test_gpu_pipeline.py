@@ -1,0 +1,101 @@
+"""GPU tests of candidate extraction, the Adam update and the refinement
+loop (through the C ABI binding)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_03296_amd as kbm
+    kbm.lib()
+    return kbm
+
+
+def _fake_results(seed, Hr, Wr, K, V):
+    """Result arrays drawn directly (not produced by a search)."""
+    rng = np.random.default_rng(seed)
+    lh = rng.normal(size=(Hr, Wr, K)).round(2).astype(np.float32)   # ties
+    lh[rng.random(lh.shape) < 0.1] = -np.inf
+    lh.flat[3] = np.nan
+    vidx = rng.integers(0, V, size=lh.shape).astype(np.int32)
+    vidx[~np.isfinite(lh)] = -1
+    flux = rng.normal(size=lh.shape).astype(np.float32)
+    nobs = rng.integers(0, 30, size=lh.shape).astype(np.int16)
+    keep = rng.integers(0, 2 ** 62, size=lh.shape).astype(np.int64)
+    vels = rng.uniform(-50, 50, size=(V, 2)).astype(np.float32)
+    cu = lambda a: torch.from_numpy(a).cuda()
+    res = dict(lh=cu(lh), vel_idx=cu(vidx), flux=cu(flux), n_obs=cu(nobs),
+               keep=cu(keep), lh_raw=None)
+    return res, lh, vidx, flux, nobs, keep, vels
+
+
+@pytest.mark.parametrize("n_max,lh_min", [(1, -np.inf), (37, -np.inf), (500, 0.5),
+                                          (10 ** 6, -np.inf), (0, 0.0), (20, 9.0)])
+def test_extract_top_exact(kbm, oracle_mod, n_max, lh_min):
+    Hr, Wr, K, V = 33, 70, 5, 17
+    res, lh, vidx, flux, nobs, keep, vels = _fake_results(7, Hr, Wr, K, V)
+    out = kbm.extract_top(res, vels, n_max, lh_min, region_origin=(4, 9))
+    torch.cuda.synchronize()
+    want = oracle_mod.extract_top(lh, n_max, lh_min)
+    got = out["index"].cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+    if len(want):
+        pix = want // K
+        exp_params = np.stack([4 + pix % Wr, 9 + pix // Wr,
+                               vels[vidx.ravel()[want], 0], vels[vidx.ravel()[want], 1]],
+                              axis=1).astype(np.float32)
+        np.testing.assert_array_equal(out["params"].cpu().numpy(), exp_params)
+        np.testing.assert_array_equal(out["lh"].cpu().numpy(), lh.ravel()[want])
+        np.testing.assert_array_equal(out["flux"].cpu().numpy(), flux.ravel()[want])
+        np.testing.assert_array_equal(out["n_obs"].cpu().numpy(), nobs.ravel()[want])
+        np.testing.assert_array_equal(out["keep"].cpu().numpy(), keep.ravel()[want])
+
+
+def test_adam_step_matches_oracle(kbm, oracle_mod):
+    rng = np.random.default_rng(3)
+    n = 1000
+    p0 = rng.normal(size=(n, 4)).astype(np.float32)
+    lr = np.array([0.3, 0.3, 0.1, 0.1], np.float32)
+    p, m, v = (torch.from_numpy(p0.copy()).cuda(), torch.zeros(n, 4, device="cuda"),
+               torch.zeros(n, 4, device="cuda"))
+    rp, rm, rv = p0.astype(np.float64), np.zeros((n, 4)), np.zeros((n, 4))
+    for step in range(1, 8):
+        g = rng.normal(size=(n, 4)).astype(np.float32)
+        kbm.adam_step(p, torch.from_numpy(g).cuda(), m, v, lr, step)
+        rp, rm, rv = oracle_mod.adam_step(rp, g, rm, rv, lr.astype(np.float64), step)
+    np.testing.assert_allclose(p.cpu().numpy(), rp, rtol=1e-5, atol=1e-5)
+
+
+def test_refine_recovers_injected_tracks(kbm):
+    """Perturbed true tracks (+/-0.5 px, +/-5 px/day) climb back: the
+    likelihood rises and the start-position error shrinks."""
+    st = synth.make_config(2, size=(900, 600), n_vel=(4, 4))
+    psi, phi = kbm.make_planes(torch.from_numpy(st.sci).cuda(),
+                               torch.from_numpy(st.var).cuda(),
+                               torch.from_numpy(st.mask).cuda(), st.psf, st.times)
+    truth = np.array([[s["x0"], s["y0"], s["vx"], s["vy"]] for s in st.sources])
+    rng = np.random.default_rng(4)
+    reps = 20
+    t = np.repeat(truth, reps, axis=0)
+    pert = t + np.concatenate([rng.uniform(-0.5, 0.5, (len(t), 2)),
+                               rng.uniform(-5, 5, (len(t), 2))], axis=1)
+    p0 = torch.from_numpy(pert.astype(np.float32)).cuda()
+    l0 = kbm.refine_forward(psi, phi, st.times, p0).cpu().numpy()
+    p1, l1 = kbm.refine(psi, phi, st.times, p0, steps=50)
+    l1 = l1.cpu().numpy()
+    p1 = p1.cpu().numpy()
+    assert np.median(l1 - l0) > 0
+    assert np.mean(l1 >= l0 - 1e-3) > 0.9
+    tm = st.times.max()
+    err0 = np.hypot(pert[:, 0] - t[:, 0] + (pert[:, 2] - t[:, 2]) * tm / 2,
+                    pert[:, 1] - t[:, 1] + (pert[:, 3] - t[:, 3]) * tm / 2)
+    err1 = np.hypot(p1[:, 0] - t[:, 0] + (p1[:, 2] - t[:, 2]) * tm / 2,
+                    p1[:, 1] - t[:, 1] + (p1[:, 3] - t[:, 3]) * tm / 2)
+    assert np.median(err1) < np.median(err0)
