@@ -4,15 +4,21 @@
 One step = the whole hot path on one DECam-CCD-shaped stack (2048 wide x
 4096 high, T = 26 epochs over 3 nights, 1% masked, PSF sigma 1.4 on 9x9,
 50 injected sources, 128 x 128 velocity grid over 90-500 px/day and +/-30
-degrees, K = 8, sigma_G on, min_obs 20): likelihood planes from the images,
-then the exhaustive search with the in-line sigma_G filter and per-pixel
-top-K.  Inputs are synthetic (seeded, shaped like the paper's DECam NEO
-difference images) and resident in HBM before timing starts.
+degrees, K = 8, sigma_G on, min_obs 20):
+  1. likelihood planes from the images (kbm_make_planes);
+  2. the exhaustive search with the in-line sigma_G filter and per-pixel
+     top-K, run by the batched persistent kernel (one launch, replayed from
+     its captured HIP graph);
+  3. extraction of the global top 10^5 result slots;
+  4. 50 Adam steps of adjoint (bilinear) refinement of those candidates.
+Inputs are synthetic (seeded, shaped like the paper's DECam NEO difference
+images) and resident in HBM before timing starts.
 
 Prints one JSON line.  The metric counts trajectory-epoch evaluations
 nominally, W * H * V * T per search, whatever the validity or pruning.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -26,6 +32,44 @@ sys.path.insert(0, ROOT)
 # operations: 256 CUs x 64 lanes/clk x 2.4 GHz.  The published 157.3 TFLOP/s
 # counts an FMA as two flops and packed FP32 as two lanes.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+# Kernel sources of the persistent search kernel; a traffic figure taken
+# with hardware counters is reported only while these are unchanged.
+KERNEL_SOURCES = ["batch_kernels.h", "batch_nw1.hip", "batch_nw4.hip",
+                  "search_kernels.h", "kbm_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_kernel_c2_traffic.md")
+N_CANDIDATES = 100_000
+REFINE_STEPS = 50
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2109_03296_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the persistent kernel from the committed
+    counter summary, or None when it is missing or was taken on other
+    kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -96,12 +140,21 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the batched-vs-per-stack comparison after timing")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the persistent kernel's schedule first")
     ap.add_argument("--size", type=str, default=None,
                     help="WxH override for quick runs (not the benchmark workload)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--print-hash", action="store_true",
+                    help="print the persistent kernel's source hash and exit")
     args = ap.parse_args()
+    if args.print_hash:
+        print(kernel_source_hash())
+        return
     if args.calib_copy:
         import torch
         n = args.calib_copy * (1 << 20) // 4
@@ -139,47 +192,75 @@ def main():
     sp = kbm.SearchParams(k=prm["k"], min_obs=prm["min_obs"], sigmag=bool(prm["sigmag"]),
                           q_lo=prm["q_lo"], q_hi=prm["q_hi"], coeff=prm["coeff"],
                           n_sigma=prm["n_sigma"])
-    ws_bytes = kbm.search_workspace_size([(T, H, W, st.times, st.vels)], [sp])
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    psi = torch.empty_like(sci)
+    phi = torch.empty_like(sci)
     stream = torch.cuda.current_stream()
+    kbm.make_planes(sci, var, mask, st.psf, st.times, out=(psi, phi))
+    log("building the persistent-search plan (tables, queues, graph capture)")
+    plan = kbm.BatchedSearch([dict(psi=psi, phi=phi, times=st.times, vels=st.vels,
+                                   params=sp)],
+                             tune=kbm.TUNE_AUTO if args.tune else kbm.TUNE_DEFAULT)
+    log(f"schedule {plan.schedule}")
+    res = plan.results[0]
+    ex_ws = torch.empty(max(kbm.extract_workspace_size(H, W, prm["k"], V), 1),
+                        dtype=torch.uint8, device=dev)
 
-    ev = []
+    stages = []
+    kernel_ms = []
+    last = {}
 
     def step(record):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e2 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        psi, phi = kbm.make_planes(sci, var, mask, st.psf, st.times)
-        e1.record(stream)
-        out = kbm.search(psi, phi, st.times, st.vels, sp, workspace=ws)
-        e2.record(stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        kbm.make_planes(sci, var, mask, st.psf, st.times, out=(psi, phi))
+        ev[1].record(stream)
+        plan.run()
+        ev[2].record(stream)
+        cand = kbm.extract_top(res, st.vels, N_CANDIDATES, workspace=ex_ws)
+        ev[3].record(stream)
+        p_ref, lh_ref = kbm.refine(psi, phi, st.times, cand["params"],
+                                   keep=cand["keep"], steps=REFINE_STEPS)
+        ev[4].record(stream)
         if record:
-            ev.append((e0, e1, e2))
-        return out
+            stages.append(ev)
+            kernel_ms.append(plan.kernel_ms())
+        last.update(cand=cand, params=p_ref, lh=lh_ref)
 
     for i in range(args.warmup):
         log(f"warmup step {i + 1}/{args.warmup}")
         step(False)
         torch.cuda.synchronize()
+    if plan.check():
+        raise RuntimeError("persistent search: a dependency wait gave up")
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
     t0 = time.perf_counter()
     for i in range(args.steps):
-        out = step(True)
+        step(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if plan.check():
+        raise RuntimeError("persistent search: a dependency wait gave up")
     ms_step = (t1 - t0) * 1e3 / args.steps
-    planes_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / len(ev)
-    search_ms = sum(b.elapsed_time(c) for _, b, c in ev) / len(ev)
-    log(f"step {ms_step:.1f} ms (planes {planes_ms:.2f} ms, search {search_ms:.1f} ms)")
+
+    def avg(a, b):
+        return sum(e[a].elapsed_time(e[b]) for e in stages) / len(stages)
+    st_ms = {"planes": avg(0, 1), "search_graph": avg(1, 2),
+             "search_kernel": sum(kernel_ms) / len(kernel_ms),
+             "extract": avg(2, 3), "refine": avg(3, 4)}
+    log(f"step {ms_step:.1f} ms; stages " +
+        ", ".join(f"{k} {v:.2f}" for k, v in st_ms.items()))
 
     traj_epochs = float(W) * H * V * T
     value = traj_epochs / (ms_step / 1e3)
     ops = search_alg_ops(T, prm["sigmag"])
-    achieved = traj_epochs * ops / (search_ms / 1e3) / 1e12
-    o = out["n_obs"]
+    achieved = traj_epochs * ops / (st_ms["search_kernel"] / 1e3) / 1e12
+    o = res["n_obs"]
     valid_frac = float((o >= prm["min_obs"]).float().mean().item())
+    cand = last["cand"]
+    lh0 = cand["lh"].double()
+    n_cand = int(lh0.numel())
+    lh_ref = last["lh"].double()
     rec = {
         "metric": "trajectory-epoch evals/s",
         "value": value,
@@ -194,19 +275,34 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "decam-ccd stack 2048x4096, T=26 (3 nights), "
-                               "128x128 velocity grid, sigma_G on, top-8 per pixel"
+                               "128x128 velocity grid, sigma_G on, top-8 per pixel, "
+                               "top-1e5 extraction, 50-step adjoint refinement"
                    if size is None else f"reduced {W}x{H} stack (not the benchmark)",
                    "width": W, "height": H, "epochs": T, "velocities": V,
                    "k": prm["k"], "min_obs": prm["min_obs"], "sigmag": True,
-                   "psf": st.psf.shape[0], "mask_rate": 0.01},
-        "planes_ms": planes_ms,
-        "search_ms": search_ms,
+                   "psf": st.psf.shape[0], "mask_rate": 0.01,
+                   "candidates": N_CANDIDATES, "refine_steps": REFINE_STEPS},
+        "stages_ms": st_ms,
+        "schedule": plan.schedule,
         "top_slot_filled_frac": valid_frac,
-        "roofline": {"bound": "alu", "kernel": "search_kernel",
+        "refine": {"candidates": n_cand,
+                   "median_lh_grid": float(lh0.median().item()) if n_cand else None,
+                   "median_lh_refined": float(lh_ref.median().item()) if n_cand else None,
+                   "frac_improved": float((lh_ref >= lh0).double().mean().item())
+                   if n_cand else None},
+        "roofline": {"bound": "alu", "kernel": "batch_kernel",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "ops_per_traj_epoch": ops, "traffic": None},
+                     "ops_per_traj_epoch": ops, "traffic": measured_traffic(),
+                     "kernel_source_hash": kernel_source_hash()},
     }
+    if not args.no_check:
+        log("checking the batched results against the per-stack search")
+        ref = kbm.search(psi, phi, st.times, st.vels, sp)
+        torch.cuda.synchronize()
+        same = all(torch.equal(ref[k], res[k]) for k in ref if ref[k] is not None)
+        rec["batched_vs_plain"] = {"identical": bool(same)}
+    plan.close()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(st, prm, log)

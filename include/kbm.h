@@ -144,6 +144,88 @@ kbm_status kbm_search(const kbm_stack *stacks, const float *const *psi,
                       size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * Batched persistent search - kbm_search's result for many independent
+ * stacks (the paper searches each CCD of each pointing separately, Section
+ * 2, and runs the search many times over, Section 3) from ONE persistent
+ * kernel launch, replayed from a captured HIP graph.
+ *
+ * Work items are (stack, 64-pixel row tile, block of vel_block velocities).
+ * Eight queues, one per XCD, each hold a contiguous strip of every stack's
+ * tiles, ordered velocity-block-major and, within a block, by descending
+ * cost per item (longest-processing-time first).  Workgroups take items
+ * from their own XCD's queue with an atomic counter and then from the other
+ * queues.  A tile's running top-K lists pass from one velocity block to the
+ * next through the workspace; a per-tile progress counter orders them.  The
+ * item that covers a tile's last velocity block writes its results.
+ * Results are bit-identical to kbm_search on the same inputs (the ranking
+ * is a total order, so the schedule cannot change it).
+ *
+ * Limits: T <= 32, k <= 8, and T*H*W*8 bytes of packed planes per stack
+ * below 2^32 (otherwise KBM_ERR_UNSUPPORTED: use kbm_search).
+ */
+typedef struct {
+    int32_t vel_block;     /* velocities per work item, >= 32 */
+    int32_t tile_cols;     /* super-tile width in 64-pixel tiles: 1,2,4,8,16 */
+    int32_t tile_rows;     /* super-tile height in rows: 1,2,4,...,64 */
+    int32_t waves;         /* wavefronts per workgroup sharing a tile: 1 or 4 */
+    int32_t blocks_per_cu; /* persistent workgroups per CU; 0 = all that fit */
+    float probe_ms;        /* out: time of this schedule on the autotuner's
+                              probe (0 when not tuned) */
+} kbm_schedule;
+
+#define KBM_TUNE_DEFAULT 0 /* built-in schedule */
+#define KBM_TUNE_AUTO 1    /* time candidate schedules on a probe, keep the
+                              fastest (cached per process by batch shape) */
+#define KBM_TUNE_GIVEN 2   /* use *schedule as given */
+
+typedef struct kbm_batch kbm_batch; /* opaque plan with its captured graph */
+
+/* Bytes of device workspace kbm_batch_create needs (any schedule). */
+kbm_status kbm_batch_workspace_size(const kbm_stack *stacks,
+                                    const kbm_search_params *p,
+                                    int32_t num_stacks, size_t *bytes);
+
+/*
+ * kbm_batch_create - validate, build the offset tables and work queues in
+ * the workspace, pick the schedule (tune), and capture the launch sequence
+ * (clear control block -> pack planes -> persistent search) into a graph.
+ * Synchronous: returns when the workspace is ready.  With KBM_TUNE_AUTO it
+ * runs the search several times on a probe (a fraction of every stack's
+ * tiles), overwriting `out`.
+ *
+ *   stacks, p, out, psi, phi : as kbm_search.  The device pointers (psi,
+ *       phi, result arrays, workspace) are baked into the graph: they must
+ *       stay valid until kbm_batch_destroy; their contents may change
+ *       between runs (new images of the same geometry).
+ *   schedule : in for KBM_TUNE_GIVEN; out (may be NULL otherwise): the
+ *       schedule in use.
+ *   batch    : out, the plan; free with kbm_batch_destroy.
+ */
+kbm_status kbm_batch_create(const kbm_stack *stacks, const float *const *psi,
+                            const float *const *phi,
+                            const kbm_search_params *p, kbm_results *out,
+                            int32_t num_stacks, void *workspace,
+                            size_t workspace_bytes, int32_t tune,
+                            kbm_schedule *schedule, hipStream_t stream,
+                            kbm_batch **batch);
+
+/* Enqueue one run of the captured graph on `stream` (asynchronous). */
+kbm_status kbm_batch_run(kbm_batch *b, hipStream_t stream);
+
+/* Synchronise `stream` and report whether a dependency wait of the last
+ * completed run gave up (stalled != 0: that run's results are not valid).
+ * Each wait is bounded, so a run always ends. */
+kbm_status kbm_batch_check(kbm_batch *b, hipStream_t stream, int32_t *stalled);
+
+/* Duration in ms of the persistent search kernel in the last completed run,
+ * from HIP events recorded around it inside the graph; waits for that run.
+ * KBM_ERR_UNSUPPORTED if the runtime refused event nodes at capture. */
+kbm_status kbm_batch_kernel_ms(kbm_batch *b, float *ms);
+
+/* Release the plan (graph, stream, events, host buffers); NULL is a no-op. */
+kbm_status kbm_batch_destroy(kbm_batch *b);
+
+/*
  * kbm_sigmag_filter - the sigma_G lightcurve filter of Section 3.1 on n
  * independent lightcurves, with the same rule and precision as kbm_search.
  *

@@ -26,7 +26,8 @@ __all__ = [
     "KbmError", "lib", "make_planes", "search", "search_batched",
     "search_workspace_size", "sigmag_filter", "refine_forward",
     "refine_backward", "TrajLH", "SearchParams", "MAX_EPOCHS", "MAX_K",
-    "MAX_PSF", "extract_top", "adam_step", "refine",
+    "MAX_PSF", "extract_top", "adam_step", "refine", "BatchedSearch",
+    "Schedule", "batch_workspace_size", "extract_workspace_size",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -92,8 +93,29 @@ def lib():
                                       C.c_size_t, P]
         L.kbm_adam_step.argtypes = [P, P, P, P, i64, i32, P, f64, f64, f64,
                                     i32, i32, P]
+        L.kbm_batch_workspace_size.argtypes = [P, P, i32, P]
+        L.kbm_batch_create.argtypes = [P, P, P, P, P, i32, P, C.c_size_t, i32,
+                                       P, P, P]
+        L.kbm_batch_run.argtypes = [P, P]
+        L.kbm_batch_check.argtypes = [P, P, P]
+        L.kbm_batch_destroy.argtypes = [P]
+        L.kbm_batch_kernel_ms.argtypes = [P, P]
         _lib = L
         return L
+
+
+class Schedule(C.Structure):
+    """Schedule of the batched persistent search (see ``kbm_schedule``)."""
+    _fields_ = [("vel_block", C.c_int32), ("tile_cols", C.c_int32),
+                ("tile_rows", C.c_int32), ("waves", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("probe_ms", C.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+TUNE_DEFAULT, TUNE_AUTO, TUNE_GIVEN = 0, 1, 2
+BATCH_MAX_EPOCHS, BATCH_MAX_K = 32, 8
 
 
 def _check(func, status):
@@ -137,11 +159,12 @@ def _stack(T, H, W, times):
     return _Stack(W, H, T, times.ctypes.data), times
 
 
-def make_planes(sci, var, mask, psf, times=None, stream=None):
+def make_planes(sci, var, mask, psf, times=None, stream=None, out=None):
     """psi, phi = correlation of I*w with the PSF and of w with PSF^2
     (w = inverse variance, zero where masked or unusable).  ``sci``/``var``
     are float32 ``[T][H][W]`` device tensors, ``mask`` uint8 or None, ``psf``
-    a host ``[k][k]`` array."""
+    a host ``[k][k]`` array.  ``out=(psi, phi)`` writes into given tensors
+    (e.g. the planes a BatchedSearch was built on)."""
     T, H, W = sci.shape
     _dev(sci, torch.float32, "sci")
     _dev(var, torch.float32, "var", sci.shape)
@@ -151,8 +174,13 @@ def make_planes(sci, var, mask, psf, times=None, stream=None):
     if psf.ndim != 2 or psf.shape[0] != psf.shape[1]:
         raise ValueError("psf must be square")
     st, _t = _stack(T, H, W, np.zeros(T) if times is None else times)
-    psi = torch.empty_like(sci)
-    phi = torch.empty_like(sci)
+    if out is not None:
+        psi, phi = out
+        _dev(psi, torch.float32, "psi", sci.shape)
+        _dev(phi, torch.float32, "phi", sci.shape)
+    else:
+        psi = torch.empty_like(sci)
+        phi = torch.empty_like(sci)
     _check("kbm_make_planes", lib().kbm_make_planes(
         C.byref(st), _ptr(sci), _ptr(var), _ptr(mask),
         psf.ctypes.data_as(C.c_void_p), psf.shape[0], _ptr(psi), _ptr(phi),
@@ -214,11 +242,36 @@ def search_workspace_size(shapes_times_vels, params: Sequence[SearchParams]) -> 
     return int(nbytes.value)
 
 
-def search_batched(items, want_lh_raw=True, workspace=None, stream=None):
+def _batch_ok(items):
+    for it in items:
+        T, H, W = it["psi"].shape
+        p = it.get("params") or SearchParams()
+        if T > BATCH_MAX_EPOCHS or p.k > BATCH_MAX_K or 8 * T * H * W >= 2 ** 32:
+            return False
+    return True
+
+
+def search_batched(items, want_lh_raw=True, workspace=None, stream=None,
+                   persistent=None, tune=TUNE_DEFAULT):
     """Search several independent stacks in one call.
 
     ``items`` is a list of dicts with keys psi, phi, times, vels, params
-    (a SearchParams).  Returns one result dict per stack."""
+    (a SearchParams).  Returns one result dict per stack.
+
+    ``persistent``: True runs the batched persistent kernel (one launch for
+    all stacks, see BatchedSearch), False the per-stack launch sequence of
+    kbm_search, None picks the persistent kernel when every stack is within
+    its limits (T <= 32, k <= 8)."""
+    if persistent is None:
+        persistent = len(items) > 1 and _batch_ok(items)
+    if persistent:
+        with BatchedSearch(items, want_lh_raw=want_lh_raw, tune=tune,
+                           workspace=workspace, stream=stream) as b:
+            b.run(stream)
+            if b.check(stream):
+                raise KbmError("kbm_batch_run", "device error",
+                               "a dependency wait of the persistent search gave up")
+            return b.results
     n = len(items)
     stacks = (_Stack * n)()
     ps = (_SearchParams * n)()
@@ -261,7 +314,130 @@ def search(psi, phi, times, vels, params: Optional[SearchParams] = None,
     if kw:
         p = SearchParams(**{**p.__dict__, **kw})
     return search_batched([dict(psi=psi, phi=phi, times=times, vels=vels,
-                                params=p)], want_lh_raw, workspace, stream)[0]
+                                params=p)], want_lh_raw, workspace, stream,
+                          persistent=False)[0]
+
+
+def _batch_structs(items):
+    n = len(items)
+    stacks = (_Stack * n)()
+    ps = (_SearchParams * n)()
+    hold = []
+    for j, it in enumerate(items):
+        psi = it["psi"]
+        T, H, W = psi.shape
+        stacks[j], t = _stack(T, H, W, it["times"])
+        p = it.get("params") or SearchParams()
+        ps[j], v = _params(p, it["vels"], W, H)
+        hold += [t, v]
+    return stacks, ps, hold
+
+
+def batch_workspace_size(items) -> int:
+    """Workspace bytes of a BatchedSearch over ``items`` (dicts with psi
+    (or shape via a tensor), times, vels, params)."""
+    stacks, ps, _hold = _batch_structs(items)
+    nbytes = C.c_size_t(0)
+    _check("kbm_batch_workspace_size", lib().kbm_batch_workspace_size(
+        stacks, ps, len(items), C.byref(nbytes)))
+    return int(nbytes.value)
+
+
+class BatchedSearch:
+    """Batched persistent search over many stacks: one persistent kernel
+    launch per run, replayed from a HIP graph captured at construction.
+
+    ``items`` as for search_batched.  ``tune``: TUNE_DEFAULT, TUNE_AUTO
+    (time candidate schedules on a probe and keep the fastest), or a
+    Schedule / dict of its fields (used as given).  The plane tensors,
+    results and workspace are held by this object: refill ``psi``/``phi`` in
+    place and call run() again to search new images of the same geometry.
+    ``results`` holds one result dict per stack (valid after run())."""
+
+    def __init__(self, items, want_lh_raw=True, tune=TUNE_DEFAULT,
+                 workspace=None, stream=None):
+        n = len(items)
+        L = lib()
+        stacks, ps, self._hold = _batch_structs(items)
+        psi_p = (C.c_void_p * n)()
+        phi_p = (C.c_void_p * n)()
+        res = (_Results * n)()
+        self.results = []
+        self._tensors = []
+        for j, it in enumerate(items):
+            psi, phi = it["psi"], it["phi"]
+            _dev(psi, torch.float32, "psi")
+            _dev(phi, torch.float32, "phi", psi.shape)
+            T, H, W = psi.shape
+            p = it.get("params") or SearchParams()
+            psi_p[j] = psi.data_ptr()
+            phi_p[j] = phi.data_ptr()
+            x0, y0, x1, y1 = p.region if p.region is not None else (0, 0, W, H)
+            o, r = _alloc_results(y1 - y0, x1 - x0, p.k, psi.device, want_lh_raw)
+            self.results.append(o)
+            res[j] = r
+            self._tensors += [psi, phi]
+        nbytes = C.c_size_t(0)
+        _check("kbm_batch_workspace_size",
+               L.kbm_batch_workspace_size(stacks, ps, n, C.byref(nbytes)))
+        if workspace is None or workspace.numel() < nbytes.value:
+            workspace = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8,
+                                    device=items[0]["psi"].device)
+        self.workspace = workspace
+        sched = Schedule()
+        if isinstance(tune, (Schedule, dict)):
+            src = tune.as_dict() if isinstance(tune, Schedule) else tune
+            for f, _ in Schedule._fields_:
+                if f in src:
+                    setattr(sched, f, src[f])
+            mode = TUNE_GIVEN
+        else:
+            mode = int(tune)
+        handle = C.c_void_p()
+        _check("kbm_batch_create", L.kbm_batch_create(
+            stacks, psi_p, phi_p, ps, res, n, _ptr(workspace), workspace.numel(),
+            mode, C.byref(sched), _stream(stream), C.byref(handle)))
+        self._h = handle
+        self.schedule = sched.as_dict()
+
+    def run(self, stream=None):
+        """Enqueue one run (graph launch) on ``stream``."""
+        if not self._h:
+            raise KbmError("kbm_batch_run", "invalid argument", "plan is closed")
+        _check("kbm_batch_run", lib().kbm_batch_run(self._h, _stream(stream)))
+        return self.results
+
+    def check(self, stream=None) -> bool:
+        """Synchronise and return True if the last run's dependency waits
+        gave up (its results are then invalid)."""
+        stalled = C.c_int32(0)
+        _check("kbm_batch_check", lib().kbm_batch_check(
+            self._h, _stream(stream), C.byref(stalled)))
+        return bool(stalled.value)
+
+    def kernel_ms(self) -> float:
+        """Duration of the persistent kernel in the last completed run (ms),
+        from HIP events inside the graph (waits for that run)."""
+        ms = C.c_float(0.0)
+        _check("kbm_batch_kernel_ms", lib().kbm_batch_kernel_ms(self._h, C.byref(ms)))
+        return float(ms.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().kbm_batch_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sigmag_filter(psi_curve, phi_curve=None, valid=None, q_lo=0.25,
@@ -347,6 +523,14 @@ class TrajLH(torch.autograd.Function):
         _, gp = refine_backward(psi, phi, ctx.times, params,
                                 grad_lh.contiguous().float(), keep, gpsi, gphi)
         return gp, gpsi, gphi, None, None
+
+
+def extract_workspace_size(Hr, Wr, k, num_vel) -> int:
+    """Workspace bytes extract_top needs for [Hr][Wr][k] results."""
+    nb = C.c_size_t(0)
+    _check("kbm_extract_workspace_size", lib().kbm_extract_workspace_size(
+        int(Hr), int(Wr), int(k), int(num_vel), C.byref(nb)))
+    return int(nb.value)
 
 
 def extract_top(res, vels, n_max, lh_min=-float("inf"), region_origin=(0, 0),

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "search_host.h"
 #include "search_kernels.h"
 
 namespace kbm {
@@ -21,13 +22,7 @@ __global__ __launch_bounds__(256) void pack_prep_kernel(
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     bool bad = false;
-    for (size_t j = i; j < n; j += stride) {
-        const float a = psi[j], b = phi[j];
-        const bool ok = b > 0.0f && isfinite(b) && isfinite(a);
-        const float sb = sqrtf(b);
-        pk[j] = ok ? make_float2(a / sb, sb) : make_float2(__builtin_nanf(""), 0.0f);
-        bad |= !ok;
-    }
+    for (size_t j = i; j < n; j += stride) pk[j] = pack_sample(psi[j], phi[j], bad);
     if (__any(bad) && (threadIdx.x % WAVE) == 0) atomicOr(flags, 1);
 }
 
@@ -69,11 +64,7 @@ void launch_finalize(const SearchArgs &a, hipStream_t stream) {
     else launch_finalize_t<64>(a, stream);
 }
 
-// Workspace per stack: packed planes, tables, flags, top-K state.
-struct StackLayout {
-    size_t pk_off, pk_bytes, tab_off, tab_bytes, flags_off, stl_off, sti_off, end;
-    size_t off_rel, lin_rel, box_rel, mbox_rel, rank_rel;  // in the table block
-};
+}  // namespace
 
 StackLayout layout(const kbm_stack &s, const kbm_search_params &p,
                    size_t start) {
@@ -148,11 +139,6 @@ kbm_status check_search(const kbm_stack *stacks, const kbm_search_params *p,
     return KBM_OK;
 }
 
-// Offset tables of one stack, laid out as in the workspace table block:
-// (dx, dy) = floor(v t + 1/2) in FP64 with t from the earliest epoch (this
-// translation unit is compiled with -ffp-contract=off, so the product is
-// rounded before the addition), the linear element offset dy*W + dx, and
-// each velocity's offset bounding box.
 // Tables of one stack, laid out as in the workspace table block:
 //  * off16: (dx, dy) = floor(v t + 1/2) in FP64 with t from the earliest
 //    epoch (this translation unit is compiled with -ffp-contract=off, so the
@@ -216,7 +202,6 @@ void make_tables(const kbm_stack &s, const kbm_search_params &p,
     }
 }
 
-}  // namespace
 }  // namespace srch
 }  // namespace kbm
 

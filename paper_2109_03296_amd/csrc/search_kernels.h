@@ -55,12 +55,6 @@ namespace srch {
 #ifndef KBM_MAX_WAVES_PER_SIMD
 #define KBM_MAX_WAVES_PER_SIMD 8
 #endif
-#ifndef KBM_STAGGER
-#define KBM_STAGGER 1
-#endif
-#ifndef KBM_PIPE
-#define KBM_PIPE 0
-#endif
 #ifndef KBM_NW
 #define KBM_NW 1
 #endif
@@ -73,6 +67,21 @@ constexpr int ST_TILES = ST_X * ST_Y;
 constexpr int VCHUNK = KBM_VCHUNK;  // velocities per launch
 constexpr int NW = KBM_NW;          // waves per workgroup sharing a tile
 constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer descriptor, CDNA
+
+// Constant address space: tables and argument blocks that no kernel writes
+// while the search runs are read through it, so uniform reads stay scalar
+// loads even in kernels that store elsewhere.
+#define KBM_CONST __attribute__((address_space(4)))
+template <class P>
+__device__ __forceinline__ const KBM_CONST P *cst(const P *p) {
+    return (const KBM_CONST P *)p;
+}
+
+// Entry i of a constant int4 table.
+__device__ __forceinline__ int4 ld_box(const int4 *t, int i) {
+    const KBM_CONST int *p = (const KBM_CONST int *)t + 4 * (size_t)i;
+    return make_int4(p[0], p[1], p[2], p[3]);
+}
 
 struct SearchArgs {
     const float2 *pk;         // [T][H][W] (nu, s)
@@ -104,7 +113,8 @@ __device__ __forceinline__ bool ranks_before(float la, int ia, float lb,
     return la > lb || (la == lb && ia < ib);
 }
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const SearchArgs &a) {
+template <class A>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const A &a) {
     return __builtin_amdgcn_make_buffer_rsrc((void *)a.pk, (short)0,
                                              (int)a.pk_bytes, BUF_DWORD3);
 }
@@ -117,12 +127,22 @@ __device__ __forceinline__ float2 ld_plane(__amdgpu_buffer_rsrc_t r,
 
 // Element e of the packed planes, clamped into the planes (an out-of-image
 // lane's offset may wrap; its value is discarded by the caller).
-template <bool SINGLE>
-__device__ __forceinline__ float2 ld_elem(const SearchArgs &a,
+template <bool SINGLE, class A>
+__device__ __forceinline__ float2 ld_elem(const A &a,
                                           __amdgpu_buffer_rsrc_t r, uint32_t e) {
     const uint32_t c = min(e, a.n_elem - 1u);
     if (SINGLE) return ld_plane(r, c * 8u, 0u);
     return a.pk[c];
+}
+
+// Packed sample of one pixel-epoch: (psi / sqrt(phi), sqrt(phi)), both
+// correctly rounded binary32, or (NaN, 0) when the pixel-epoch is unusable
+// (phi <= 0 or a non-finite value).  Sets bad for an unusable one.
+__device__ __forceinline__ float2 pack_sample(float psi, float phi, bool &bad) {
+    const bool ok = phi > 0.0f && isfinite(phi) && isfinite(psi);
+    const float sb = sqrtf(phi);
+    bad |= !ok;
+    return ok ? make_float2(psi / sb, sb) : make_float2(__builtin_nanf(""), 0.0f);
 }
 
 struct Score {
@@ -133,8 +153,8 @@ struct Score {
 // Filtered (or plain) likelihood of one lightcurve.  For i < T, nu[i] is NaN
 // for an unusable epoch and s[i] = 0; entries i >= T are padding (+inf, 0).
 // SEL selects the NaN handling needed when unusable epochs may be present.
-template <int TM, bool SEL, bool EXACT>
-__device__ __forceinline__ Score score(const SearchArgs &a,
+template <int TM, bool SEL, bool EXACT, class A>
+__device__ __forceinline__ Score score(const A &a,
                                        const float (&nu)[TM],
                                        const float (&s)[TM], int nv) {
     const int T = EXACT ? TM : a.T;
@@ -142,7 +162,8 @@ __device__ __forceinline__ Score score(const SearchArgs &a,
     float P = 0.0f, F = 0.0f;
     uint32_t lo = 0, hi = 0;
     if (a.sigmag) {
-        const int rl = a.ranks[nv], rm = a.ranks[65 + nv], rh = a.ranks[130 + nv];
+        const KBM_CONST int *rk = cst(a.ranks);
+        const int rl = rk[nv], rm = rk[65 + nv], rh = rk[130 + nv];
         const SigmaGCut c = sigmag_cut<TM, SEL>(nu, rl, rm, rh, a.coeff, a.n_sigma);
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
@@ -179,8 +200,8 @@ __device__ __forceinline__ Score score(const SearchArgs &a,
 // Clean, exact-T fast path with the default quantiles (0.25, 0.75): every
 // epoch is usable, the nearest ranks floor(q (T-1) + 1/2) are compile-time
 // constants, and the kept sums zero s instead of selecting twice.
-template <int T>
-__device__ __forceinline__ float score_fixed(const SearchArgs &a,
+template <int T, class A>
+__device__ __forceinline__ float score_fixed(const A &a,
                                              const float (&nu)[T],
                                              const float (&s)[T]) {
     constexpr int RL = (T + 1) / 4, RM = T / 2, RH = (3 * T - 1) / 4;
@@ -204,11 +225,11 @@ __device__ __forceinline__ float score_fixed(const SearchArgs &a,
 }
 
 // Whole-wave in-bounds load: the per-epoch offset is wave-uniform.
-template <int TM, bool CLEAN, bool EXACT, bool SINGLE>
-__device__ __forceinline__ int load_fast(const SearchArgs &a,
+template <int TM, bool CLEAN, bool EXACT, bool SINGLE, class A>
+__device__ __forceinline__ int load_fast(const A &a,
                                          __amdgpu_buffer_rsrc_t rs,
                                          uint32_t lane, uint32_t wave_e,
-                                         const uint32_t *lv, float (&nu)[TM],
+                                         const KBM_CONST uint32_t *lv, float (&nu)[TM],
                                          float (&s)[TM]) {
     const int T = EXACT ? TM : a.T;
     int nv = 0;
@@ -230,11 +251,11 @@ __device__ __forceinline__ int load_fast(const SearchArgs &a,
 }
 
 // General load with per-lane bounds checks.
-template <int TM, bool EXACT, bool SINGLE>
-__device__ __forceinline__ int load_slow(const SearchArgs &a,
+template <int TM, bool EXACT, bool SINGLE, class A>
+__device__ __forceinline__ int load_slow(const A &a,
                                          __amdgpu_buffer_rsrc_t rs, int x,
-                                         int y, const int *ov,
-                                         const uint32_t *lv, float (&nu)[TM],
+                                         int y, const KBM_CONST int *ov,
+                                         const KBM_CONST uint32_t *lv, float (&nu)[TM],
                                          float (&s)[TM]) {
     const int T = EXACT ? TM : a.T;
     const uint32_t pix = (uint32_t)(y * a.W + x);
@@ -274,14 +295,20 @@ __device__ __forceinline__ bool map_tile(const SearchArgs &a, int &tx, int &ty) 
     return tx < a.tiles_x && ty < a.Hr;
 }
 
-template <int TM, int KM, bool CLEAN, bool EXACT, bool SINGLE>
-__device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
+// Sweep velocities [v_begin, v_end) for the tile's 64 start pixels.  With
+// first set the running lists start empty, else they are read from the
+// workspace; they are written back at the end.  mL/mI point to an LDS block
+// of (NW-1)*KM*WAVE entries each (unused when NW == 1).
+template <int TM, int KM, bool CLEAN, bool EXACT, bool SINGLE, int NWT = NW, class A>
+__device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
+                                          int v_begin, int v_end, bool first,
+                                          float *mL, int *mI) {
     // NW waves share this tile's 64 start pixels and interleave the chunk's
     // velocities (wave w takes v = v_begin + w, w + NW, ...), so at any time
     // they read nearly the same plane rows: lines are shared through L1 and
     // the per-XCD footprint of a velocity step shrinks NW-fold.
     const unsigned lane = threadIdx.x % WAVE;
-    const int w = NW > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)) : 0;
+    const int w = NWT > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)) : 0;
     const int rx = tx * WAVE + (int)lane, ry = ty;
     const bool active = rx < a.Wr;
     const int xw = a.x0 + tx * WAVE;
@@ -301,7 +328,7 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
         if (slot < 0) {
             kL[j] = INFINITY;
             kI[j] = -2;
-        } else if (a.first || !active || w != 0) {
+        } else if (first || !active || w != 0) {
             kL[j] = -INFINITY;
             kI[j] = -1;
         } else {
@@ -311,19 +338,15 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
     }
 
     const uint32_t wave_e = (uint32_t)(y * a.W + xw);
-    const int nvel = a.v_end - a.v_begin;
-    const int rot = KBM_STAGGER > 1 ? (int)((blockIdx.x / NUM_XCD) % KBM_STAGGER) * nvel / KBM_STAGGER : 0;
-    for (int vv = w; vv < nvel; vv += NW) {
-        int v = a.v_begin + vv + rot;
-        if (v >= a.v_end) v -= nvel;
-        const int4 bx = a.vbox[v];
+    for (int v = v_begin + w; v < v_end; v += NWT) {
+        const int4 bx = ld_box(a.vbox, v);
         const bool fast = xw + bx.x >= 0 &&
                           xw + (WAVE - 1) + bx.y < a.W && y + bx.z >= 0 &&
                           y + bx.w < a.H;
         if (!fast) {
             // Sound skip: if fewer than min_obs epochs can hold any lane of
             // this wave in the image (per axis), no lane reaches min_obs.
-            const int4 mb = a.mbox[v];
+            const int4 mb = ld_box(a.mbox, v);
             if (xw + mb.x > a.W - 1 || xw + (WAVE - 1) + mb.y < 0 ||
                 y + mb.z > a.H - 1 || y + mb.w < 0)
                 continue;
@@ -333,14 +356,14 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
         Score sc;
         if (fast) {
             nv = load_fast<TM, CLEAN, EXACT, SINGLE>(a, rs, lane, wave_e,
-                                                     a.lin + (size_t)v * T, nu, s);
+                                                     cst(a.lin) + (size_t)v * T, nu, s);
             if (EXACT && CLEAN && a.defq)
                 sc.L = score_fixed<TM>(a, nu, s);
             else
                 sc = score<TM, !CLEAN, EXACT>(a, nu, s, nv);
         } else {
-            nv = load_slow<TM, EXACT, SINGLE>(a, rs, x, y, a.off16 + (size_t)v * T,
-                                              a.lin + (size_t)v * T, nu, s);
+            nv = load_slow<TM, EXACT, SINGLE>(a, rs, x, y, cst(a.off16) + (size_t)v * T,
+                                              cst(a.lin) + (size_t)v * T, nu, s);
             sc = score<TM, true, EXACT>(a, nu, s, nv);
         }
         if (active && nv >= a.min_obs && isfinite(sc.L) &&
@@ -360,25 +383,23 @@ __device__ __forceinline__ void run_chunk(const SearchArgs &a, int tx, int ty) {
             }
         }
     }
-    if (NW > 1) {
+    if (NWT > 1) {
         // Merge the waves' lists into wave 0's through LDS.  The ranking
         // compares velocity indices on ties, so the merge order is immaterial.
-        __shared__ float mL[NW > 1 ? NW - 1 : 1][KM][WAVE];
-        __shared__ int mI[NW > 1 ? NW - 1 : 1][KM][WAVE];
         if (w > 0) {
 #pragma unroll
             for (int j = 0; j < KM; ++j) {
-                mL[w - 1][j][lane] = kL[j];
-                mI[w - 1][j][lane] = kI[j];
+                mL[((w - 1) * KM + j) * WAVE + lane] = kL[j];
+                mI[((w - 1) * KM + j) * WAVE + lane] = kI[j];
             }
         }
         __syncthreads();
         if (w != 0) return;
-        for (int o = 0; o < NW - 1; ++o) {
+        for (int o = 0; o < NWT - 1; ++o) {
 #pragma unroll
             for (int j = 0; j < KM; ++j) {
-                const float L = mL[o][j][lane];
-                const int v = mI[o][j][lane];
+                const float L = mL[(o * KM + j) * WAVE + lane];
+                const int v = mI[(o * KM + j) * WAVE + lane];
                 if (v >= 0 && ranks_before(L, v, kL[KM - 1], kI[KM - 1])) {
                     kL[KM - 1] = L;
                     kI[KM - 1] = v;
@@ -427,137 +448,28 @@ __device__ __forceinline__ void topk_insert(float (&kL)[KM], int (&kI)[KM],
     }
 }
 
-// One velocity of the software-pipelined sweep (clean stacks, exact T,
-// single buffer).  cur holds this velocity's samples when it is on the fast
-// path (loaded one step earlier); the next velocity's loads are issued into
-// nxt before this velocity is scored, so they travel while the lane sorts.
-template <int T, int KM>
-__device__ __forceinline__ void pipe_step(const SearchArgs &a,
-                                          __amdgpu_buffer_rsrc_t rs,
-                                          unsigned lane, int x, int y, int xw,
-                                          uint32_t wave_e, bool active, int v,
-                                          bool fast_v, int vn, bool fast_n,
-                                          float (&cn)[T], float (&cs)[T],
-                                          float (&nn)[T], float (&ns)[T],
-                                          float (&kL)[KM], int (&kI)[KM]) {
-    if (fast_n)
-        load_fast<T, true, true, true>(a, rs, lane, wave_e, a.lin + (size_t)vn * T, nn, ns);
-    float L;
-    int nv = T;
-    if (fast_v) {
-        if (a.defq) {
-            L = score_fixed<T>(a, cn, cs);
-        } else {
-            L = score<T, false, true>(a, cn, cs, T).L;
-        }
-    } else {
-        const int4 mb = a.mbox[v];
-        if (xw + mb.x > a.W - 1 || xw + (WAVE - 1) + mb.y < 0 ||
-            y + mb.z > a.H - 1 || y + mb.w < 0)
-            return;
-        nv = load_slow<T, true, true>(a, rs, x, y, a.off16 + (size_t)v * T,
-                                      a.lin + (size_t)v * T, cn, cs);
-        L = score<T, true, true>(a, cn, cs, nv).L;
-    }
-    if (active && nv >= a.min_obs && isfinite(L) &&
-        ranks_before(L, v, kL[KM - 1], kI[KM - 1]))
-        topk_insert<KM>(kL, kI, L, v);
-}
-
-template <int T, int KM>
-__device__ __forceinline__ void run_chunk_pipe(const SearchArgs &a, int tx, int ty) {
-    const unsigned lane = threadIdx.x;
-    const int rx = tx * WAVE + (int)lane, ry = ty;
-    const bool active = rx < a.Wr;
-    const int xw = a.x0 + tx * WAVE;
-    const int x = xw + (int)lane, y = a.y0 + ry;
-    const size_t npix = (size_t)a.Wr * a.Hr;
-    const size_t pix = (size_t)ry * a.Wr + (active ? rx : 0);
-    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a);
-
-    float kL[KM];
-    int kI[KM];
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-        const int slot = j - (KM - a.K);
-        if (slot < 0) {
-            kL[j] = INFINITY;
-            kI[j] = -2;
-        } else if (a.first || !active) {
-            kL[j] = -INFINITY;
-            kI[j] = -1;
-        } else {
-            kL[j] = a.stL[(size_t)slot * npix + pix];
-            kI[j] = a.stI[(size_t)slot * npix + pix];
-        }
-    }
-    const uint32_t wave_e = (uint32_t)(y * a.W + xw);
-    const int nvel = a.v_end - a.v_begin;
-    const int rot = KBM_STAGGER > 1 ? (int)((blockIdx.x / NUM_XCD) % KBM_STAGGER) * nvel / KBM_STAGGER : 0;
-    auto vel_at = [&](int vv) {
-        int v = a.v_begin + vv + rot;
-        return v >= a.v_end ? v - nvel : v;
-    };
-    auto is_fast = [&](int v) {
-        const int4 bx = a.vbox[v];
-        return xw + bx.x >= 0 && xw + (WAVE - 1) + bx.y < a.W && y + bx.z >= 0 &&
-               y + bx.w < a.H;
-    };
-    float An[T], As[T], Bn[T], Bs[T];
-    int v = vel_at(0);
-    bool fv = is_fast(v);
-    if (fv) load_fast<T, true, true, true>(a, rs, lane, wave_e, a.lin + (size_t)v * T, An, As);
-    for (int vv = 0; vv < nvel; vv += 2) {
-        const bool has1 = vv + 1 < nvel;
-        const int v1 = has1 ? vel_at(vv + 1) : v;
-        const bool f1 = has1 && is_fast(v1);
-        pipe_step<T, KM>(a, rs, lane, x, y, xw, wave_e, active, v, fv, v1, f1,
-                         An, As, Bn, Bs, kL, kI);
-        if (!has1) break;
-        const bool has2 = vv + 2 < nvel;
-        const int v2 = has2 ? vel_at(vv + 2) : v1;
-        const bool f2 = has2 && is_fast(v2);
-        pipe_step<T, KM>(a, rs, lane, x, y, xw, wave_e, active, v1, f1, v2, f2,
-                         Bn, Bs, An, As, kL, kI);
-        v = v2;
-        fv = f2;
-    }
-    if (!active) return;
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-        const int slot = j - (KM - a.K);
-        if (slot >= 0) {
-            a.stL[(size_t)slot * npix + pix] = kL[j];
-            a.stI[(size_t)slot * npix + pix] = kI[j];
-        }
-    }
-}
-
 template <int TM, int KM, bool EXACT, bool SINGLE>
 __global__ __launch_bounds__(WAVE * NW)
 __attribute__((amdgpu_waves_per_eu(1, KBM_MAX_WAVES_PER_SIMD)))
 void search_chunk_kernel(SearchArgs a) {
+    __shared__ float mL[NW > 1 ? (NW - 1) * KM * WAVE : 1];
+    __shared__ int mI[NW > 1 ? (NW - 1) * KM * WAVE : 1];
     int tx, ty;
     if (!map_tile(a, tx, ty)) return;
-    if (a.flags[0] == 0) {
-        if (KBM_PIPE && NW == 1 && EXACT && SINGLE)
-            run_chunk_pipe<TM, KM>(a, tx, ty);
-        else
-            run_chunk<TM, KM, true, EXACT, SINGLE>(a, tx, ty);
-    } else {
-        run_chunk<TM, KM, false, EXACT, SINGLE>(a, tx, ty);
-    }
+    if (cst(a.flags)[0] == 0)
+        run_chunk<TM, KM, true, EXACT, SINGLE>(a, tx, ty, a.v_begin, a.v_end, a.first, mL, mI);
+    else
+        run_chunk<TM, KM, false, EXACT, SINGLE>(a, tx, ty, a.v_begin, a.v_end, a.first, mL, mI);
 }
 
-// Re-evaluate each pixel's K winners and write all result fields.
-template <int TM, bool SINGLE>
-__global__ __launch_bounds__(256) void finalize_kernel(SearchArgs a) {
+// Re-evaluate the K winners of start pixel (x, y) (flat result index pix
+// within the region) from the running lists and write all result fields.
+template <int TM, bool EXACT, bool SINGLE, class A>
+__device__ __forceinline__ void finalize_pixel(const A &a,
+                                               __amdgpu_buffer_rsrc_t rs, int x,
+                                               int y, size_t pix) {
     const size_t npix = (size_t)a.Wr * a.Hr;
-    const size_t pix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= npix) return;
-    const int rx = (int)(pix % a.Wr), ry = (int)(pix / a.Wr);
-    const int x = a.x0 + rx, y = a.y0 + ry;
-    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a);
+    const int T = EXACT ? TM : a.T;
     for (int slot = 0; slot < a.K; ++slot) {
         const size_t o = pix * a.K + slot;
         const int vi = a.stI[(size_t)slot * npix + pix];
@@ -571,9 +483,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(SearchArgs a) {
             continue;
         }
         float nu[TM], s[TM];
-        const int nv = load_slow<TM, false, SINGLE>(a, rs, x, y, a.off16 + (size_t)vi * a.T,
-                                                     a.lin + (size_t)vi * a.T, nu, s);
-        const Score sc = score<TM, true, false>(a, nu, s, nv);
+        const int nv = load_slow<TM, EXACT, SINGLE>(a, rs, x, y, cst(a.off16) + (size_t)vi * T,
+                                                    cst(a.lin) + (size_t)vi * T, nu, s);
+        const Score sc = score<TM, true, EXACT>(a, nu, s, nv);
         a.lh[o] = sc.L;
         a.flux[o] = sc.flux;
         a.vidx[o] = vi;
@@ -583,7 +495,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(SearchArgs a) {
             float P = 0.0f, F = 0.0f;
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
-                if (i < a.T) {
+                if (i < T) {
                     P = fmaf(nu[i] == nu[i] ? nu[i] : 0.0f, s[i], P);
                     F = fmaf(s[i], s[i], F);
                 }
@@ -591,6 +503,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(SearchArgs a) {
             a.lh_raw[o] = P / sqrtf(F);
         }
     }
+}
+
+template <int TM, bool SINGLE>
+__global__ __launch_bounds__(256) void finalize_kernel(SearchArgs a) {
+    const size_t npix = (size_t)a.Wr * a.Hr;
+    const size_t pix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= npix) return;
+    const int rx = (int)(pix % a.Wr), ry = (int)(pix / a.Wr);
+    finalize_pixel<TM, false, SINGLE>(a, plane_rsrc(a), a.x0 + rx, a.y0 + ry, pix);
 }
 
 // Launch the chunk sequence for one kernel variant.

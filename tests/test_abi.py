@@ -123,6 +123,50 @@ def test_search_validation_and_workspace_size(L):
                         C.c_size_t(1 << 30), None) == 1
 
 
+def test_batch_validation(L):
+    import paper_2109_03296_amd as kbm
+    st, t = _stack()
+    vels = np.array([[1.0, 2.0], [0.0, 0.0], [-3.0, 1.0]], np.float32)
+    p = _params(vels)
+    nb, ns = C.c_size_t(0), C.c_size_t(0)
+    assert L.kbm_batch_workspace_size(C.byref(st), C.byref(p), 1, C.byref(nb)) == 0
+    assert L.kbm_search_workspace_size(C.byref(st), C.byref(p), 1, C.byref(ns)) == 0
+    assert nb.value > ns.value   # per-stack blocks plus queues and counters
+    # beyond the persistent kernel's limits: unsupported (kbm_search covers it)
+    st33, t33 = _stack(T=33)
+    assert L.kbm_batch_workspace_size(C.byref(st33), C.byref(p), 1, C.byref(nb)) == 2
+    p9 = _params(vels, k=9)
+    assert L.kbm_batch_workspace_size(C.byref(st), C.byref(p9), 1, C.byref(nb)) == 2
+    assert L.kbm_batch_workspace_size(C.byref(st), C.byref(p), 0, C.byref(nb)) == 1
+    planes = (C.c_void_p * 1)(0x1000)
+    res = (kbm._Results * 1)(kbm._Results(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, None))
+    h = C.c_void_p()
+    big = C.c_size_t(1 << 30)
+    # bad tune mode, bad given schedules, NULL handle, small workspace
+    assert L.kbm_batch_create(C.byref(st), planes, planes, C.byref(p), res, 1, FAKE, big,
+                              7, None, None, C.byref(h)) == 1
+    assert L.kbm_batch_create(C.byref(st), planes, planes, C.byref(p), res, 1, FAKE, big,
+                              2, None, None, C.byref(h)) == 1
+    for bad in (dict(vel_block=16), dict(tile_cols=3), dict(tile_rows=128),
+                dict(waves=2), dict(blocks_per_cu=-1)):
+        sc = kbm.Schedule(256, 4, 16, 1, 0, 0.0)
+        for f, v in bad.items():
+            setattr(sc, f, v)
+        assert L.kbm_batch_create(C.byref(st), planes, planes, C.byref(p), res, 1, FAKE,
+                                  big, 2, C.byref(sc), None, C.byref(h)) == 1, bad
+    assert L.kbm_batch_create(C.byref(st), planes, planes, C.byref(p), res, 1, FAKE, big,
+                              0, None, None, None) == 1
+    assert L.kbm_batch_create(C.byref(st), planes, planes, C.byref(p), res, 1, FAKE,
+                              C.c_size_t(16), 0, None, None, C.byref(h)) == 5
+    assert h.value is None
+    assert L.kbm_batch_run(None, None) == 1
+    stalled = C.c_int32(0)
+    assert L.kbm_batch_check(None, None, C.byref(stalled)) == 1
+    ms = C.c_float(0.0)
+    assert L.kbm_batch_kernel_ms(None, C.byref(ms)) == 1
+    assert L.kbm_batch_destroy(None) == 0
+
+
 def test_sigmag_and_refine_validation(L):
     assert L.kbm_sigmag_filter(FAKE, None, None, 10, 0, 0.25, 0.75, 0.7413, 2.0,
                                FAKE, None, None) == 1

@@ -1,0 +1,200 @@
+"""GPU: the batched persistent search (one persistent launch for many
+stacks, replayed from a captured HIP graph) against the per-stack search
+(bit-identical: the ranking is a total order, so no schedule can change the
+result) and against the FP64 oracle (protocol B: both read the oracle's
+planes rounded to float32).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kbm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2109_03296_amd as kbm
+    kbm.lib()
+    return kbm
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# (stack factory, parameter overrides, region): uneven sizes, epoch counts
+# 3..32, k 1..8, filter on and off, masked pixels, a start region, an empty
+# region and a one-column image.
+BATCH = [
+    (lambda: synth.make_config(2, size=(300, 200), n_vel=(16, 24)), {}, None),
+    (lambda: synth.make_config(1), {}, None),
+    (lambda: synth.tiny_stack(21, W=96, H=40, T=10, n_vel=70, max_speed=12.0),
+     dict(k=8, min_obs=6), None),
+    (lambda: synth.tiny_stack(22, W=130, H=33, T=30, n_vel=45, mask_rate=0.2,
+                              max_speed=3.0), dict(k=4, min_obs=10), None),
+    (lambda: synth.tiny_stack(23, W=64, H=17, T=32, n_vel=33, max_speed=2.0),
+     dict(k=8, sigmag=0, min_obs=1), None),
+    (lambda: synth.make_config(2, size=(300, 200), n_vel=(12, 12)),
+     dict(k=6), (5, 3, 290, 150)),
+    (lambda: synth.tiny_stack(24, W=1, H=23, T=3, n_vel=40, max_speed=4.0),
+     dict(k=2, min_obs=1), None),
+    (lambda: synth.tiny_stack(25, W=40, H=30, T=17, n_vel=50), dict(k=3),
+     (4, 4, 4, 9)),
+]
+
+
+def _params(kbm, st, over, region):
+    p = dict(st.params)
+    p.update(over)
+    reg = region or (0, 0, st.W, st.H)
+    sp = kbm.SearchParams(k=p["k"], min_obs=p["min_obs"], sigmag=bool(p["sigmag"]),
+                          q_lo=p["q_lo"], q_hi=p["q_hi"], coeff=p["coeff"],
+                          n_sigma=p["n_sigma"], region=reg)
+    return p, reg, sp
+
+
+@pytest.fixture(scope="module")
+def batch(kbm, oracle_mod):
+    """Stacks, their float32 oracle planes on the GPU, and the per-stack
+    search results (the reference for bit-identity)."""
+    out = []
+    for j, (make, over, region) in enumerate(BATCH):
+        st = make()
+        p, reg, sp = _params(kbm, st, over, region)
+        psi, phi = oracle_mod.planes(st.sci, st.var, st.mask, st.psf)
+        psi, phi = psi.astype(np.float32), phi.astype(np.float32)
+        item = dict(psi=_cuda(psi), phi=_cuda(phi), times=st.times, vels=st.vels,
+                    params=sp)
+        _say(f"batch stack {j}: W={st.W} H={st.H} T={st.T} V={len(st.vels)} "
+             f"k={p['k']} region={reg}")
+        plain = kbm.search(item["psi"], item["phi"], st.times, st.vels, sp)
+        out.append(dict(st=st, p=p, reg=reg, item=item, plain=plain,
+                        psi=psi, phi=phi))
+    torch.cuda.synchronize()
+    return out
+
+
+def _equal(a, b):
+    for key in ("lh", "flux", "vel_idx", "n_obs", "keep", "lh_raw"):
+        if a.get(key) is None and b.get(key) is None:
+            continue
+        assert torch.equal(a[key], b[key]), key
+
+
+def _run(kbm, batch, tune):
+    items = [b["item"] for b in batch]
+    with kbm.BatchedSearch(items, tune=tune) as plan:
+        plan.run()
+        assert not plan.check(), "dependency wait gave up"
+        return plan.results, plan.schedule
+
+
+def test_batch_matches_per_stack_search(kbm, batch):
+    _say("batch: default schedule vs per-stack search")
+    items = [b["item"] for b in batch]
+    with kbm.BatchedSearch(items) as plan:
+        plan.run()
+        assert not plan.check(), "dependency wait gave up"
+        ms = plan.kernel_ms()
+        _say(f"  schedule {plan.schedule}, kernel {ms:.3f} ms")
+        assert ms > 0.0
+        for b, r in zip(batch, plan.results):
+            _equal(r, b["plain"])
+
+
+def test_batch_protocol_B(kbm, oracle_mod, batch):
+    _say("batch: protocol B against the oracle")
+    res, _ = _run(kbm, batch, kbm.TUNE_DEFAULT)
+    for j, (b, r) in enumerate(zip(batch, res)):
+        st, p, reg = b["st"], b["p"], b["reg"]
+        ref = oracle_mod.search(b["psi"], b["phi"], st.times, st.vels, region=reg, **p)
+
+        def single(y, x, v, b=b, st=st, p=p, reg=reg):
+            o = oracle_mod.search(b["psi"], b["phi"], st.times, st.vels[v:v + 1], k=1,
+                                  region=(reg[0] + x, reg[1] + y, reg[0] + x + 1,
+                                          reg[1] + y + 1),
+                                  **{k: p[k] for k in ("min_obs", "sigmag", "q_lo",
+                                                       "q_hi", "coeff", "n_sigma")})
+            return float(o["lh"][0, 0, 0])
+        stats = P.compare_search(r, ref, single)
+        _say(f"  stack {j}: {stats}")
+
+
+SCHEDULES = [
+    dict(vel_block=32, tile_cols=1, tile_rows=1, waves=1, blocks_per_cu=1),
+    dict(vel_block=1000, tile_cols=16, tile_rows=64, waves=4, blocks_per_cu=0),
+    dict(vel_block=64, tile_cols=2, tile_rows=32, waves=4, blocks_per_cu=2),
+    dict(vel_block=96, tile_cols=8, tile_rows=8, waves=1, blocks_per_cu=0),
+]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "vb%d_%dx%d_w%d_b%d" % (
+    s["vel_block"], s["tile_cols"], s["tile_rows"], s["waves"], s["blocks_per_cu"]))
+def test_batch_schedules_identical(kbm, batch, sched):
+    _say(f"batch: schedule {sched}")
+    res, used = _run(kbm, batch, sched)
+    for f in ("vel_block", "tile_cols", "tile_rows", "waves"):
+        assert used[f] == sched[f]
+    for b, r in zip(batch, res):
+        _equal(r, b["plain"])
+
+
+def test_batch_graph_replay_and_refill(kbm, batch):
+    _say("batch: graph replays and refilled planes")
+    items = [dict(b["item"], psi=b["item"]["psi"].clone(), phi=b["item"]["phi"].clone())
+             for b in batch]
+    with kbm.BatchedSearch(items) as plan:
+        first = None
+        for rep in range(3):
+            plan.run()
+            assert not plan.check()
+            snap = [{k: (v.clone() if v is not None else None) for k, v in r.items()}
+                    for r in plan.results]
+            if first is None:
+                first = snap
+            else:
+                for a, b in zip(snap, first):
+                    _equal(a, b)
+            # eager work between replays
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            torch.cuda.synchronize()
+            del junk
+        # new images of the same geometry: scale psi (L scales with it)
+        for it in items:
+            it["psi"].mul_(-0.5)
+        plan.run()
+        assert not plan.check()
+        for it, r in zip(items, plan.results):
+            ref = kbm.search(it["psi"], it["phi"], it["times"], it["vels"], it["params"])
+            _equal(r, ref)
+
+
+def test_batch_autotune(kbm, batch):
+    _say("batch: autotuned schedule")
+    res, sched = _run(kbm, batch, kbm.TUNE_AUTO)
+    _say(f"  tuned {sched}")
+    assert sched["vel_block"] >= 32 and sched["waves"] in (1, 4)
+    assert sched["blocks_per_cu"] >= 1 and sched["probe_ms"] > 0
+    for b, r in zip(batch, res):
+        _equal(r, b["plain"])
+
+
+def test_search_batched_default_is_persistent(kbm, batch):
+    _say("batch: search_batched picks the persistent kernel")
+    items = [b["item"] for b in batch]
+    res = kbm.search_batched(items)
+    torch.cuda.synchronize()
+    for b, r in zip(batch, res):
+        _equal(r, b["plain"])
