@@ -173,7 +173,8 @@ typedef struct {
                               probe (0 when not tuned) */
 } kbm_schedule;
 
-#define KBM_TUNE_DEFAULT 0 /* built-in schedule */
+#define KBM_TUNE_DEFAULT 0 /* built-in schedule: vel_block 1024, 4 x 16
+                              super-tiles, 4 waves, all that fit */
 #define KBM_TUNE_AUTO 1    /* time candidate schedules on a probe, keep the
                               fastest (cached per process by batch shape) */
 #define KBM_TUNE_GIVEN 2   /* use *schedule as given */
@@ -217,12 +218,7 @@ kbm_status kbm_batch_run(kbm_batch *b, hipStream_t stream);
  * Each wait is bounded, so a run always ends. */
 kbm_status kbm_batch_check(kbm_batch *b, hipStream_t stream, int32_t *stalled);
 
-/* Duration in ms of the persistent search kernel in the last completed run,
- * from HIP events recorded around it inside the graph; waits for that run.
- * KBM_ERR_UNSUPPORTED if the runtime refused event nodes at capture. */
-kbm_status kbm_batch_kernel_ms(kbm_batch *b, float *ms);
-
-/* Release the plan (graph, stream, events, host buffers); NULL is a no-op. */
+/* Release the plan (graph, stream, host buffers); NULL is a no-op. */
 kbm_status kbm_batch_destroy(kbm_batch *b);
 
 /*

@@ -99,7 +99,6 @@ def lib():
         L.kbm_batch_run.argtypes = [P, P]
         L.kbm_batch_check.argtypes = [P, P, P]
         L.kbm_batch_destroy.argtypes = [P]
-        L.kbm_batch_kernel_ms.argtypes = [P, P]
         _lib = L
         return L
 
@@ -414,13 +413,6 @@ class BatchedSearch:
         _check("kbm_batch_check", lib().kbm_batch_check(
             self._h, _stream(stream), C.byref(stalled)))
         return bool(stalled.value)
-
-    def kernel_ms(self) -> float:
-        """Duration of the persistent kernel in the last completed run (ms),
-        from HIP events inside the graph (waits for that run)."""
-        ms = C.c_float(0.0)
-        _check("kbm_batch_kernel_ms", lib().kbm_batch_kernel_ms(self._h, C.byref(ms)))
-        return float(ms.value)
 
     def close(self):
         if getattr(self, "_h", None):

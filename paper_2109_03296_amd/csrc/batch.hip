@@ -60,6 +60,11 @@ struct Sched {
 
 bool pow2_in(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
 
+// Built-in schedule: 1024 velocities per item, 4 wavefronts per workgroup
+// sharing a tile (each sweeps every fourth velocity), 256 px x 16 row
+// super-tiles, as many workgroups as fit.
+Sched default_sched() { return Sched{1024, 4, 16, 4, 0}; }
+
 }  // namespace batch
 }  // namespace kbm
 
@@ -85,9 +90,7 @@ struct kbm_batch {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the persistent kernel
-    bool timed = false;                       // events are graph nodes
-    uint32_t *host_word = nullptr;            // pinned
+    uint32_t *host_word = nullptr;  // pinned
 };
 
 namespace kbm {
@@ -306,7 +309,7 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
     KBM_HIP(hipEventCreate(&e0));
     KBM_HIP(hipEventCreate(&e1));
     kbm_status st = KBM_OK;
-    Sched cur{256, 4, 16, 1, 0};
+    Sched cur = default_sched();
     float cur_ms = 0.0f, ms = 0.0f;
     auto run = [&](const Sched &c, float *t) -> kbm_status {
         return probe(b, c, div, stream, e0, e1, t);
@@ -323,7 +326,7 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
             }
             return s2;
         };
-        const int vbs[] = {64, 128, 512, 1024};
+        const int vbs[] = {256, 512, 2048, 4096};
         for (int v : vbs) {
             if (v / 2 >= vmax) continue;  // same single block as a smaller one
             Sched c = cur;
@@ -341,7 +344,7 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
         if (st != KBM_OK) break;
         {
             Sched c = cur;
-            c.nw = 4;
+            c.nw = cur.nw == 4 ? 1 : 4;
             if ((st = consider(c)) != KBM_OK) break;
         }
         int full = 1;
@@ -368,8 +371,6 @@ void release(kbm_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
-    if (b->ev0) (void)hipEventDestroy(b->ev0);
-    if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->host_word) (void)hipHostFree(b->host_word);
     delete b;
 }
@@ -407,7 +408,7 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
     KBM_REQUIRE(tune == KBM_TUNE_DEFAULT || tune == KBM_TUNE_AUTO || tune == KBM_TUNE_GIVEN,
                 KBM_ERR_INVALID_ARG, "kbm_batch_create: tune = %d is not a KBM_TUNE_ mode",
                 tune);
-    Sched given{256, 4, 16, 1, 0};
+    Sched given = default_sched();
     if (tune == KBM_TUNE_GIVEN) {
         KBM_REQUIRE(schedule != nullptr, KBM_ERR_INVALID_ARG,
                     "kbm_batch_create: KBM_TUNE_GIVEN needs a schedule");
@@ -543,37 +544,23 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
         set_error("kbm_batch_create: cannot create the capture stream");
         return fail(KBM_ERR_DEVICE);
     }
-    if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
-        set_error("kbm_batch_create: cannot create events");
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        set_error("kbm_batch_create: hipStreamBeginCapture failed");
         return fail(KBM_ERR_DEVICE);
     }
-    // Capture with event nodes around the persistent kernel (for timing);
-    // if the runtime refuses them, capture the kernels alone.
-    for (int with_events = 1; with_events >= 0; --with_events) {
-        if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            set_error("kbm_batch_create: hipStreamBeginCapture failed");
-            return fail(KBM_ERR_DEVICE);
-        }
-        st = with_events ? enqueue_run(b, sc, b->cap, b->ev0, b->ev1)
-                         : enqueue_run(b, sc, b->cap);
-        hipGraph_t g = nullptr;
-        const hipError_t ec = hipStreamEndCapture(b->cap, &g);
-        hipError_t ei = hipErrorUnknown;
-        if (st == KBM_OK && ec == hipSuccess && g != nullptr)
-            ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-        if (ei == hipSuccess) {
-            b->graph = g;
-            b->timed = with_events != 0;
-            break;
-        }
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipGetLastError();
-        if (!with_events) {
-            if (st == KBM_OK)
-                set_error("kbm_batch_create: graph capture failed: %s",
-                          hipGetErrorString(ec != hipSuccess ? ec : ei));
-            return fail(st != KBM_OK ? st : KBM_ERR_DEVICE);
-        }
+    st = enqueue_run(b, sc, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->cap, &g);
+    b->graph = g;
+    if (st != KBM_OK) return fail(st);
+    if (ec != hipSuccess || g == nullptr) {
+        set_error("kbm_batch_create: hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+        return fail(KBM_ERR_DEVICE);
+    }
+    const hipError_t ei = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        set_error("kbm_batch_create: hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+        return fail(KBM_ERR_DEVICE);
     }
     if (schedule) {
         schedule->vel_block = sc.vb;
@@ -605,18 +592,6 @@ extern "C" kbm_status kbm_batch_check(kbm_batch *b, hipStream_t stream, int32_t 
                            hipMemcpyDeviceToHost, stream));
     KBM_HIP(hipStreamSynchronize(stream));
     *stalled = b->host_word[0] != 0u;
-    return KBM_OK;
-}
-
-extern "C" kbm_status kbm_batch_kernel_ms(kbm_batch *b, float *ms) {
-    using namespace kbm;
-    clear_error();
-    KBM_REQUIRE(b != nullptr && ms != nullptr, KBM_ERR_INVALID_ARG,
-                "kbm_batch_kernel_ms: batch and ms must be non-NULL");
-    KBM_REQUIRE(b->timed, KBM_ERR_UNSUPPORTED,
-                "kbm_batch_kernel_ms: the graph was captured without event nodes");
-    KBM_HIP(hipEventSynchronize(b->ev1));
-    KBM_HIP(hipEventElapsedTime(ms, b->ev0, b->ev1));
     return KBM_OK;
 }
 

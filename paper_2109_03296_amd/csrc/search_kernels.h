@@ -44,10 +44,10 @@ namespace kbm {
 namespace srch {
 
 #ifndef KBM_ST_X
-#define KBM_ST_X 4
+#define KBM_ST_X 2
 #endif
 #ifndef KBM_ST_Y
-#define KBM_ST_Y 16
+#define KBM_ST_Y 32
 #endif
 #ifndef KBM_VCHUNK
 #define KBM_VCHUNK 256
@@ -56,7 +56,7 @@ namespace srch {
 #define KBM_MAX_WAVES_PER_SIMD 8
 #endif
 #ifndef KBM_NW
-#define KBM_NW 1
+#define KBM_NW 4
 #endif
 
 constexpr int WAVE = 64;

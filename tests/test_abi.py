@@ -162,8 +162,6 @@ def test_batch_validation(L):
     assert L.kbm_batch_run(None, None) == 1
     stalled = C.c_int32(0)
     assert L.kbm_batch_check(None, None, C.byref(stalled)) == 1
-    ms = C.c_float(0.0)
-    assert L.kbm_batch_kernel_ms(None, C.byref(ms)) == 1
     assert L.kbm_batch_destroy(None) == 0
 
 

@@ -107,9 +107,7 @@ def test_batch_matches_per_stack_search(kbm, batch):
     with kbm.BatchedSearch(items) as plan:
         plan.run()
         assert not plan.check(), "dependency wait gave up"
-        ms = plan.kernel_ms()
-        _say(f"  schedule {plan.schedule}, kernel {ms:.3f} ms")
-        assert ms > 0.0
+        _say(f"  schedule {plan.schedule}")
         for b, r in zip(batch, plan.results):
             _equal(r, b["plain"])
 

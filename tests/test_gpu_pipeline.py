@@ -99,3 +99,31 @@ def test_refine_recovers_injected_tracks(kbm):
     err1 = np.hypot(p1[:, 0] - t[:, 0] + (p1[:, 2] - t[:, 2]) * tm / 2,
                     p1[:, 1] - t[:, 1] + (p1[:, 3] - t[:, 3]) * tm / 2)
     assert np.median(err1) < np.median(err0)
+
+
+def test_coarse_to_fine_pipeline(kbm, oracle_mod):
+    """Coarse grid -> top-N -> refinement on a reduced full-pipeline stack
+    (T = 60 over 5 nights): the extracted grid hits equal the oracle's
+    global top-N of the same search, and refinement does not lower the
+    likelihood of most candidates."""
+    from paper_2109_03296_amd.pipeline import coarse_to_fine
+    st = synth.make_config(5, size=(256, 192), n_vel=(6, 8))
+    p = st.params
+    psi, phi = oracle_mod.planes(st.sci, st.var, st.mask, st.psf)
+    psi32, phi32 = psi.astype(np.float32), phi.astype(np.float32)
+    gpsi = torch.from_numpy(psi32).cuda()
+    gphi = torch.from_numpy(phi32).cuda()
+    sp = kbm.SearchParams(k=p["k"], min_obs=p["min_obs"], sigmag=True)
+    n = 300
+    out = coarse_to_fine(gpsi, gphi, st.times, st.vels, sp, n, steps=20)
+    ref = oracle_mod.search(psi32, phi32, st.times, st.vels, **p)
+    idx = oracle_mod.extract_top(ref["lh"], n)
+    assert out["grid_lh"].shape[0] == idx.size
+    got = out["grid_lh"].cpu().numpy().astype(np.float64)
+    want = ref["lh"].ravel()[idx]
+    assert np.all(np.abs(got - want) <= 1e-4 * np.maximum(np.abs(want), 1.0))
+    lh0 = out["grid_lh"].double()
+    lh1 = out["lh"].double()
+    assert torch.isfinite(out["params"]).all()
+    assert float((lh1 >= lh0 - 1e-3 * lh0.abs().clamp(min=1)).double().mean()) >= 0.9
+    assert all(v > 0 for v in out["ms"].values())
