@@ -151,6 +151,9 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--print-hash", action="store_true",
                     help="print the persistent kernel's source hash and exit")
+    ap.add_argument("--workload", choices=("ccd", "batch62"), default="ccd",
+                    help="ccd: the DECam-CCD stack (default); batch62: 62 stacks of "
+                         "uneven sizes and epoch counts in one persistent launch")
     args = ap.parse_args()
     if args.print_hash:
         print(kernel_source_hash())
@@ -170,6 +173,9 @@ def main():
               "single MI355X (stacks are independent; see the sharding notes). "
               "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch62":
+        return bench_batch62(args)
 
     import numpy as np
     import torch
@@ -306,6 +312,120 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(st, prm, log)
+    print(json.dumps(rec), flush=True)
+
+
+def bench_batch62(args):
+    """62 independent stacks (sides drawn from 512..4096, T in [10, 30] over
+    3 nights, PSF sigma in [1, 2], 1% mask, 20 sources each, 64 x 64
+    velocities, K = 8, sigma_G on) searched by one persistent launch.  A
+    step = planes of every stack + one run of the search graph."""
+    import concurrent.futures as cf
+
+    import torch
+
+    import paper_2109_03296_amd as kbm
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    specs = synth.make_batched_specs(62)
+    log(f"generating {len(specs)} stacks ({sum(s['W'] * s['H'] * s['T'] for s in specs) / 1e9:.2f}e9 "
+        f"pixel-epochs) on {min(16, os.cpu_count() or 1)} threads")
+    items, geo = [], []
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        for j, st in enumerate(ex.map(synth.make_batched_stack, specs)):
+            sci = torch.from_numpy(st.sci).to(dev)
+            var = torch.from_numpy(st.var).to(dev)
+            mask = torch.from_numpy(st.mask).to(dev)
+            psi = torch.empty_like(sci)
+            phi = torch.empty_like(sci)
+            kbm.make_planes(sci, var, mask, st.psf, st.times, out=(psi, phi))
+            prm = st.params
+            sp = kbm.SearchParams(k=prm["k"], min_obs=prm["min_obs"], sigmag=True)
+            items.append(dict(psi=psi, phi=phi, times=st.times, vels=st.vels, params=sp))
+            geo.append(dict(sci=sci, var=var, mask=mask, psf=st.psf, T=st.T, H=st.H, W=st.W))
+            del st
+    torch.cuda.synchronize()
+    log(f"generated and uploaded in {time.perf_counter() - t0:.1f} s")
+    log("building the persistent-search plan")
+    plan = kbm.BatchedSearch(items, want_lh_raw=False,
+                             tune=kbm.TUNE_AUTO if args.tune else kbm.TUNE_DEFAULT)
+    log(f"schedule {plan.schedule}")
+    stream = torch.cuda.current_stream()
+    spans = []
+
+    def step(record):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for it, g in zip(items, geo):
+            kbm.make_planes(g["sci"], g["var"], g["mask"], g["psf"], it["times"],
+                            out=(it["psi"], it["phi"]))
+        ev[1].record(stream)
+        plan.run()
+        ev[2].record(stream)
+        if record:
+            spans.append(ev)
+
+    for i in range(args.warmup):
+        log(f"warmup step {i + 1}/{args.warmup}")
+        step(False)
+        torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    if plan.check():
+        raise RuntimeError("persistent search: a dependency wait gave up")
+    planes_ms = sum(e[0].elapsed_time(e[1]) for e in spans) / len(spans)
+    search_ms = sum(e[1].elapsed_time(e[2]) for e in spans) / len(spans)
+    te = sum(float(g["W"]) * g["H"] * g["T"] * len(it["vels"]) for g, it in zip(geo, items))
+    ops = sum(float(g["W"]) * g["H"] * g["T"] * len(it["vels"]) * search_alg_ops(g["T"], True)
+              for g, it in zip(geo, items))
+    achieved = ops / (search_ms / 1e3) / 1e12
+    log(f"step {ms_step:.1f} ms (planes {planes_ms:.1f}, search graph {search_ms:.1f})")
+    rec = {
+        "metric": "trajectory-epoch evals/s",
+        "value": te / (ms_step / 1e3),
+        "unit": "trajectory-epoch evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "62 stacks, sides from {512,1024,2048,4096}, T in [10,30], "
+                               "64x64 velocity grid, sigma_G on, top-8 per pixel, one "
+                               "persistent launch",
+                   "stacks": len(items), "trajectory_epochs": te},
+        "stages_ms": {"planes": planes_ms, "search_graph": search_ms},
+        "schedule": plan.schedule,
+        "roofline": {"bound": "alu", "kernel": "batch_kernel", "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None},
+    }
+    if not args.no_check:
+        log("per-stack search of every stack (comparison and timing)")
+        same = True
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain_ms = 0.0
+        for it, res in zip(items, plan.results):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ref = kbm.search(it["psi"], it["phi"], it["times"], it["vels"], it["params"],
+                             want_lh_raw=False)
+            e1.record(stream)
+            e1.synchronize()
+            plain_ms += e0.elapsed_time(e1)
+            same &= all(torch.equal(ref[k], res[k]) for k in ref if ref[k] is not None)
+            del ref
+        rec["batched_vs_plain"] = {"identical": bool(same), "plain_search_ms": plain_ms,
+                                   "batched_search_ms": search_ms,
+                                   "speedup": plain_ms / search_ms}
+    plan.close()
     print(json.dumps(rec), flush=True)
 
 
