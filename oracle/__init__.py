@@ -57,6 +57,8 @@ def _load():
                                     i32, P, P, P, P, P, P]
         lib.kbmo_refine.argtypes = [i32, i32, i32, P, P, P, i64, P, P, P, P,
                                     P, P, P]
+        lib.kbmo_score.argtypes = [i32, i32, i32, P, P, P, i64, P, i32, i32, f64,
+                                   f64, f64, f64, P, P, P, P, P]
         lib.kbmo_num_threads.restype = C.c_int
         _lib = lib
         return lib
@@ -179,6 +181,30 @@ def refine(psi, phi, times, params, keep=None, grad_lh=None, want_planes=False):
     if want_planes:
         return lh, gp, gpsi, gphi
     return lh, gp
+
+
+def score(psi, phi, times, params, *, min_obs=1, sigmag=1, q_lo=0.25,
+          q_hi=0.75, coeff=0.7413, n_sigma=2.0, **_ignored):
+    """Targeted evaluation of ``[n][4]`` float32 trajectories (x0, y0, vx,
+    vy) with real-valued starts: the search's L' at the pixels
+    floor(x0 + vx t + 1/2), floor(y0 + vy t + 1/2).  Returns a dict of
+    ``[n]`` arrays lh, flux, keep, n_obs, lh_raw."""
+    lib = _load()
+    psi, phi = _c(psi, np.float32), _c(phi, np.float32)
+    times = _c(times, np.float64)
+    params = _c(params, np.float32).reshape(-1, 4)
+    T, H, W = psi.shape
+    n = params.shape[0]
+    out = dict(lh=np.empty(n, np.float64), flux=np.empty(n, np.float64),
+               keep=np.empty(n, np.uint64), n_obs=np.empty(n, np.int32),
+               lh_raw=np.empty(n, np.float64))
+    rc = lib.kbmo_score(T, H, W, _p(psi), _p(phi), _p(times), n, _p(params),
+                        int(min_obs), int(sigmag), q_lo, q_hi, coeff, n_sigma,
+                        _p(out["lh"]), _p(out["flux"]), _p(out["keep"]),
+                        _p(out["n_obs"]), _p(out["lh_raw"]))
+    if rc:
+        raise ValueError("oracle score: bad arguments")
+    return out
 
 
 def extract_top(lh, n_max, lh_min=-np.inf):

@@ -325,6 +325,82 @@ int kbmo_search(int32_t T, int32_t H, int32_t W, const float *psi,
 /* Bilinear refinement objective and analytic gradient                  */
 /* ------------------------------------------------------------------ */
 
+/* Targeted evaluation of an explicit list of linear trajectories with
+ * real-valued starts (params [n][4] = x0, y0, vx, vy as float32).  Epoch i
+ * samples the pixel (floor((x0 + vx t_i) + 1/2), floor((y0 + vy t_i) + 1/2))
+ * with t_i from the earliest epoch, every product and sum rounded in FP64
+ * as written.  Usable epochs, n_obs, the sigma_G keep rule and L' are those
+ * of kbmo_search (Section 3, 3.1).  A trajectory the search would drop
+ * (n_obs < min_obs, no kept phi, non-finite L') gets lh = lh_raw = -inf,
+ * flux 0, keep 0; n_obs is reported for every trajectory. */
+int kbmo_score(int32_t T, int32_t H, int32_t W, const float *psi,
+               const float *phi, const double *times, int64_t n,
+               const float *params, int32_t min_obs, int32_t sigmag,
+               double q_lo, double q_hi, double coeff, double n_sigma,
+               double *out_lh, double *out_flux, uint64_t *out_keep,
+               int32_t *out_nobs, double *out_lh_raw)
+{
+    if (T <= 0 || T > KBMO_MAX_T || n < 0) return 1;
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma};
+    const double t0 = earliest(T, times);
+    const size_t plane = (size_t)H * W;
+
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        const double x0 = params[4 * j + 0], y0 = params[4 * j + 1];
+        const double vx = params[4 * j + 2], vy = params[4 * j + 3];
+        float ps[KBMO_MAX_T], ph[KBMO_MAX_T];
+        int part[KBMO_MAX_T];
+        int cnt = 0;
+        double sp = 0.0, sf = 0.0;
+        uint64_t valid = 0;
+        for (int i = 0; i < T; ++i) {
+            const double t = times[i] - t0;
+            const double fx = floor(x0 + vx * t + 0.5);
+            const double fy = floor(y0 + vy * t + 0.5);
+            part[i] = 0;
+            ps[i] = 0.0f;
+            ph[i] = 0.0f;
+            if (!(fx >= 0.0 && fx < (double)W && fy >= 0.0 && fy < (double)H)) continue;
+            const size_t q = (size_t)i * plane + (size_t)fy * W + (size_t)fx;
+            if (!usable(psi[q], phi[q])) continue;
+            ps[i] = psi[q];
+            ph[i] = phi[q];
+            part[i] = 1;
+            valid |= (uint64_t)1 << i;
+            ++cnt;
+            sp += (double)ps[i];
+            sf += (double)ph[i];
+        }
+        out_nobs[j] = cnt;
+        out_lh[j] = -INFINITY;
+        out_flux[j] = 0.0;
+        out_keep[j] = 0;
+        if (out_lh_raw) out_lh_raw[j] = -INFINITY;
+        if (cnt == 0 || cnt < min_obs || !(sf > 0.0)) continue;
+        uint64_t keep = valid;
+        double kp_s = sp, kf_s = sf;
+        if (sigmag) {
+            keep = sigmag_keep(T, ps, ph, part, &p);
+            kp_s = 0.0;
+            kf_s = 0.0;
+            for (int i = 0; i < T; ++i)
+                if (keep >> i & 1) {
+                    kp_s += (double)ps[i];
+                    kf_s += (double)ph[i];
+                }
+        }
+        if (!(kf_s > 0.0)) continue;
+        const double l = kp_s / sqrt(kf_s);
+        if (!isfinite(l)) continue;
+        out_lh[j] = l;
+        out_flux[j] = kp_s / kf_s;
+        out_keep[j] = keep;
+        if (out_lh_raw) out_lh_raw[j] = sp / sqrt(sf);
+    }
+    return 0;
+}
+
 static double tap(const float *plane, int H, int W, int x, int y)
 {
     if (x < 0 || x >= W || y < 0 || y >= H) return 0.0;

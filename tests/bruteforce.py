@@ -93,6 +93,41 @@ def trajectory(psi, phi, times, vel, x, y, sigmag, q_lo, q_hi, coeff, n_sigma):
                 keep=keep, lh_raw=lraw)
 
 
+def trajectory_real(psi, phi, times, prm, sigmag, q_lo, q_hi, coeff, n_sigma):
+    """One trajectory with a real-valued start: epoch i samples pixel
+    floor(x0 + vx t_i + 1/2) (Python floats, evaluated left to right)."""
+    T, H, W = psi.shape
+    x0, y0, vx, vy = (float(np.float32(v)) for v in prm)
+    t0 = min(times)
+    idx, ps, ph = [], [], []
+    for i in range(T):
+        t = float(times[i]) - float(t0)
+        xx = math.floor(x0 + vx * t + 0.5)
+        yy = math.floor(y0 + vy * t + 0.5)
+        if not (0 <= xx < W and 0 <= yy < H):
+            continue
+        a, b = psi[i, yy, xx], phi[i, yy, xx]
+        if not (b > 0 and np.isfinite(a) and np.isfinite(b)):
+            continue
+        idx.append(i)
+        ps.append(float(a))
+        ph.append(float(b))
+    if not idx:
+        return None
+    lraw = math.fsum(ps) / math.sqrt(math.fsum(ph))
+    kf = (sigmag_keep(ps, ph, q_lo, q_hi, coeff, n_sigma) if sigmag
+          else [True] * len(idx))
+    kp = [a for a, k in zip(ps, kf) if k]
+    kh = [b for b, k in zip(ph, kf) if k]
+    keep = 0
+    for i, k in zip(idx, kf):
+        if k:
+            keep |= 1 << i
+    sp, sf = math.fsum(kp), math.fsum(kh)
+    return dict(lh=sp / math.sqrt(sf), flux=sp / sf, n_obs=len(idx),
+                keep=keep, lh_raw=lraw)
+
+
 def search(psi, phi, times, vels, k, min_obs, sigmag=1, q_lo=0.25, q_hi=0.75,
            coeff=0.7413, n_sigma=2.0, region=None):
     T, H, W = psi.shape
