@@ -269,6 +269,33 @@ kbm_status kbm_refine(const kbm_stack *s, const float *psi, const float *phi,
                       float *grad_psi, float *grad_phi, hipStream_t stream);
 
 /*
+ * kbm_score_trajectories - targeted evaluation: the search's filtered
+ * likelihood (Section 3, 3.1) for an explicit list of linear trajectories
+ * with real-valued starts, e.g. refined candidates or known objects.
+ *
+ * Epoch i samples the pixel (floor((x0 + vx t_i) + 1/2), floor((y0 + vy t_i)
+ * + 1/2)) with t_i from the earliest epoch, each product and sum rounded in
+ * FP64 as written.  Usable epochs, n_obs, the sigma_G keep rule (binary32
+ * decision) and L' are those of kbm_search; an integer start on a velocity
+ * of the search grid reproduces the search's values for that trajectory.
+ * A trajectory the search would drop (n_obs < min_obs, non-finite L') gets
+ * the empty-slot values (lh = lh_raw = -inf, flux 0, keep 0); n_obs is
+ * always written.
+ *
+ *   psi, phi : device float [T][H][W]
+ *   params   : device float [n][4] (x0, y0, vx, vy), 16-byte aligned
+ *   lh, flux : device float [n]; keep: device uint64 [n]; n_obs: device
+ *              int16 [n]; lh_raw: device float [n] or NULL
+ */
+kbm_status kbm_score_trajectories(const kbm_stack *s, const float *psi,
+                                  const float *phi, int64_t n,
+                                  const float *params, int32_t min_obs,
+                                  int32_t sigmag, double q_lo, double q_hi,
+                                  double coeff, double n_sigma, float *lh,
+                                  float *flux, uint64_t *keep, int16_t *n_obs,
+                                  float *lh_raw, hipStream_t stream);
+
+/*
  * kbm_extract_top - candidate extraction: the global top-N result slots by
  * filtered likelihood with L' >= lh_min (the paper hands trajectories whose
  * recomputed likelihood clears a threshold on from the GPU, Section 3.1, and

@@ -28,6 +28,7 @@ __all__ = [
     "refine_backward", "TrajLH", "SearchParams", "MAX_EPOCHS", "MAX_K",
     "MAX_PSF", "extract_top", "adam_step", "refine", "BatchedSearch",
     "Schedule", "batch_workspace_size", "extract_workspace_size",
+    "score_trajectories",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -99,6 +100,8 @@ def lib():
         L.kbm_batch_run.argtypes = [P, P]
         L.kbm_batch_check.argtypes = [P, P, P]
         L.kbm_batch_destroy.argtypes = [P]
+        L.kbm_score_trajectories.argtypes = [P, P, P, i64, P, i32, i32, f64, f64,
+                                             f64, f64, P, P, P, P, P, P]
         _lib = L
         return L
 
@@ -515,6 +518,37 @@ class TrajLH(torch.autograd.Function):
         _, gp = refine_backward(psi, phi, ctx.times, params,
                                 grad_lh.contiguous().float(), keep, gpsi, gphi)
         return gp, gpsi, gphi, None, None
+
+
+def score_trajectories(psi, phi, times, params, params_search: Optional[SearchParams] = None,
+                       want_lh_raw=True, stream=None, **kw):
+    """The search's filtered likelihood for explicit trajectories
+    ``params`` [n][4] (x0, y0, vx, vy; real-valued starts).  ``kw`` may
+    override SearchParams fields (min_obs, sigmag, q_lo, q_hi, coeff,
+    n_sigma).  Returns a dict of [n] tensors lh, flux, keep, n_obs, lh_raw."""
+    p = params_search or SearchParams()
+    if kw:
+        p = SearchParams(**{**p.__dict__, **kw})
+    _dev(psi, torch.float32, "psi")
+    _dev(phi, torch.float32, "phi", psi.shape)
+    T, H, W = psi.shape
+    prm = _dev(params, torch.float32, "params")
+    if prm.dim() != 2 or prm.shape[1] != 4:
+        raise ValueError("params must be [n][4]")
+    n = prm.shape[0]
+    st, _t = _stack(T, H, W, times)
+    dev = psi.device
+    out = dict(lh=torch.empty(n, dtype=torch.float32, device=dev),
+               flux=torch.empty(n, dtype=torch.float32, device=dev),
+               keep=torch.empty(n, dtype=torch.int64, device=dev),
+               n_obs=torch.empty(n, dtype=torch.int16, device=dev),
+               lh_raw=torch.empty(n, dtype=torch.float32, device=dev) if want_lh_raw else None)
+    _check("kbm_score_trajectories", lib().kbm_score_trajectories(
+        C.byref(st), _ptr(psi), _ptr(phi), n, _ptr(prm), int(p.min_obs),
+        int(bool(p.sigmag)), float(p.q_lo), float(p.q_hi), float(p.coeff),
+        float(p.n_sigma), _ptr(out["lh"]), _ptr(out["flux"]), _ptr(out["keep"]),
+        _ptr(out["n_obs"]), _ptr(out["lh_raw"]), _stream(stream)))
+    return out
 
 
 def extract_workspace_size(Hr, Wr, k, num_vel) -> int:

@@ -14,21 +14,26 @@ from __future__ import annotations
 import torch
 
 from . import (SearchParams, extract_top, extract_workspace_size, refine,
-               search, search_batched)
+               score_trajectories, search, search_batched)
 
 
 def coarse_to_fine(psi, phi, times, vels, params: SearchParams, n_candidates: int,
                    lh_min: float = float("-inf"), steps: int = 50, lr_pos: float = 0.3,
                    stream=None):
     """Search ``vels`` (a coarse grid), extract the top ``n_candidates`` slots
-    with L' >= lh_min, and refine them for ``steps`` Adam steps.
+    with L' >= lh_min, refine them for ``steps`` Adam steps, and score the
+    refined trajectories with the search's filtered likelihood.
 
-    Returns a dict: params [n][4] (x0, y0, vx, vy) after refinement, lh (the
-    bilinear likelihood there, with each candidate's keep mask frozen from
-    the search), grid_params / grid_lh / keep (the extracted grid hits), and
-    stage times in ms (search, extract, refine) measured with HIP events."""
+    The refinement ascends the bilinear likelihood over all usable epochs:
+    a keep mask frozen at a coarse grid hit would hide the signal (there the
+    epochs that line up with a source are the outliers the filter drops).
+    Returns a dict: params [n][4] (x0, y0, vx, vy) after refinement; lh, keep,
+    n_obs (the search's L' of the refined trajectories, from
+    score_trajectories); lh_bilinear (the refined objective);
+    grid_params / grid_lh / grid_keep (the extracted grid hits); and stage
+    times in ms (search, extract, refine, score) from HIP events."""
     s = torch.cuda.current_stream() if stream is None else stream
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     ev[0].record(s)
     T = psi.shape[0]
     item = dict(psi=psi, phi=phi, times=times, vels=vels, params=params)
@@ -44,12 +49,16 @@ def coarse_to_fine(psi, phi, times, vels, params: SearchParams, n_candidates: in
     cand = extract_top(res, vels, n_candidates, lh_min, region_origin=origin,
                        workspace=ws, stream=stream)
     ev[2].record(s)
-    p, lh = refine(psi, phi, times, cand["params"], keep=cand["keep"], steps=steps,
-                   lr_pos=lr_pos, stream=stream)
+    p, lh_bil = refine(psi, phi, times, cand["params"], keep=None, steps=steps,
+                       lr_pos=lr_pos, stream=stream)
     ev[3].record(s)
-    ev[3].synchronize()
-    return dict(params=p, lh=lh, grid_params=cand["params"], grid_lh=cand["lh"],
-                keep=cand["keep"], results=res,
+    sc = score_trajectories(psi, phi, times, p, params, want_lh_raw=False, stream=stream)
+    ev[4].record(s)
+    ev[4].synchronize()
+    return dict(params=p, lh=sc["lh"], keep=sc["keep"], n_obs=sc["n_obs"],
+                lh_bilinear=lh_bil, grid_params=cand["params"], grid_lh=cand["lh"],
+                grid_keep=cand["keep"], results=res,
                 ms=dict(search=ev[0].elapsed_time(ev[1]),
                         extract=ev[1].elapsed_time(ev[2]),
-                        refine=ev[2].elapsed_time(ev[3])))
+                        refine=ev[2].elapsed_time(ev[3]),
+                        score=ev[3].elapsed_time(ev[4])))

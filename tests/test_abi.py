@@ -186,6 +186,20 @@ def test_sigmag_and_refine_validation(L):
                         None, None, None, None) == 0
 
 
+def test_score_validation(L):
+    st, t = _stack()
+    args = lambda n, mo=1, sg=1, ql=0.25: (C.byref(st), FAKE, FAKE, n, FAKE, mo, sg, ql, 0.75,
+                                           0.7413, 2.0, FAKE, FAKE, FAKE, FAKE, None, None)
+    assert L.kbm_score_trajectories(*args(-1)) == 1
+    assert L.kbm_score_trajectories(*args(4, mo=0)) == 1
+    assert L.kbm_score_trajectories(*args(4, sg=2)) == 1
+    assert L.kbm_score_trajectories(*args(4, ql=0.9)) == 1
+    assert L.kbm_score_trajectories(*args(0)) == 0   # nothing to do, no device
+    bad, tb = _stack(T=0)
+    assert L.kbm_score_trajectories(C.byref(bad), FAKE, FAKE, 4, FAKE, 1, 1, 0.25, 0.75,
+                                    0.7413, 2.0, FAKE, FAKE, FAKE, FAKE, None, None) == 1
+
+
 def test_binding_rejects_host_tensors():
     import torch
     import paper_2109_03296_amd as kbm
