@@ -469,7 +469,7 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
         const kbm_search_params &q = p[j];
         const srch::StackLayout l = srch::layout(s, q, cursor);
         cursor = l.end;
-        srch::make_tables(s, q, l, tables);
+        srch::make_tables(s, q, l, s.num_epochs, tables);
         st = stage_to_device(ws + l.tab_off, tables.data(), l.tab_bytes, stream);
         if (st != KBM_OK) return fail(st);
         const size_t n = (size_t)s.num_epochs * s.width * s.height;
@@ -482,6 +482,11 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
         a.pk = pk;
         a.pk_bytes = (uint32_t)l.pk_bytes;
         a.n_elem = (uint32_t)n;
+        a.am = 1;  // one descriptor (checked: packed planes below 4 GB)
+        a.split = s.num_epochs;
+        a.pk2 = pk;
+        a.pk2_bytes = 0;
+        a.n_elem2 = 0;
         a.off16 = reinterpret_cast<const int *>(ws + l.tab_off + l.off_rel);
         a.lin = reinterpret_cast<const uint32_t *>(ws + l.tab_off + l.lin_rel);
         a.vbox = reinterpret_cast<const int4 *>(ws + l.tab_off + l.box_rel);

@@ -67,14 +67,14 @@ static __device__ __noinline__ void batch_tile(const SearchArgs *descs, int s, i
     float *mL = NWT > 1 ? g_mL : nullptr;
     int *mI = NWT > 1 ? g_mI : nullptr;
     if (cst(a.flags)[0] == 0)
-        srch::run_chunk<T, BKM, true, true, true, NWT>(a, tx, ty, v0, v1, first != 0, mL, mI);
+        srch::run_chunk<T, BKM, true, true, 1, NWT>(a, tx, ty, v0, v1, first != 0, mL, mI);
     else
-        srch::run_chunk<T, BKM, false, true, true, NWT>(a, tx, ty, v0, v1, first != 0, mL, mI);
+        srch::run_chunk<T, BKM, false, true, 1, NWT>(a, tx, ty, v0, v1, first != 0, mL, mI);
     if (!last) return;
     const int w = NWT > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)) : 0;
     const int rx = tx * WAVE + (int)(threadIdx.x % WAVE);
     if (w != 0 || rx >= a.Wr) return;
-    srch::finalize_pixel<T, true, true>(a, srch::plane_rsrc(a), a.x0 + rx, a.y0 + ty,
+    srch::finalize_pixel<T, true, 1>(a, srch::plane_rsrc(a), a.x0 + rx, a.y0 + ty,
                                         (size_t)ty * a.Wr + rx);
 }
 

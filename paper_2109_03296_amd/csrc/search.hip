@@ -27,32 +27,36 @@ __global__ __launch_bounds__(256) void pack_prep_kernel(
 }
 
 // Generic (padded) buckets for epoch counts without an exact variant.
-template <int KM, bool SINGLE>
+template <int KM, int AM>
 void launch_generic_s(const SearchArgs &a, hipStream_t stream) {
-    if (a.T <= 8) launch_chunks<8, KM, false, SINGLE>(a, stream);
-    else if (a.T <= 16) launch_chunks<16, KM, false, SINGLE>(a, stream);
-    else if (a.T <= 24) launch_chunks<24, KM, false, SINGLE>(a, stream);
-    else if (a.T <= 32) launch_chunks<32, KM, false, SINGLE>(a, stream);
-    else if (a.T <= 48) launch_chunks<48, KM, false, SINGLE>(a, stream);
-    else launch_chunks<64, KM, false, SINGLE>(a, stream);
+    if (a.T <= 8) launch_chunks<8, KM, false, AM>(a, stream);
+    else if (a.T <= 16) launch_chunks<16, KM, false, AM>(a, stream);
+    else if (a.T <= 24) launch_chunks<24, KM, false, AM>(a, stream);
+    else if (a.T <= 32) launch_chunks<32, KM, false, AM>(a, stream);
+    else if (a.T <= 48) launch_chunks<48, KM, false, AM>(a, stream);
+    else launch_chunks<64, KM, false, AM>(a, stream);
 }
 
 template <int KM>
 void launch_generic(const SearchArgs &a, hipStream_t stream) {
-    if (a.pk_bytes != 0)
-        launch_generic_s<KM, true>(a, stream);
+    if (a.am == 1)
+        launch_generic_s<KM, 1>(a, stream);
+    else if (a.am == 2)
+        launch_generic_s<KM, 2>(a, stream);
     else
-        launch_generic_s<KM, false>(a, stream);
+        launch_generic_s<KM, 0>(a, stream);
 }
 
 template <int TM>
 void launch_finalize_t(const SearchArgs &a, hipStream_t stream) {
     const size_t npix = (size_t)a.Wr * a.Hr;
     const dim3 grid((unsigned)((npix + 255) / 256));
-    if (a.pk_bytes != 0)
-        hipLaunchKernelGGL((finalize_kernel<TM, true>), grid, dim3(256), 0, stream, a);
+    if (a.am == 1)
+        hipLaunchKernelGGL((finalize_kernel<TM, 1>), grid, dim3(256), 0, stream, a);
+    else if (a.am == 2)
+        hipLaunchKernelGGL((finalize_kernel<TM, 2>), grid, dim3(256), 0, stream, a);
     else
-        hipLaunchKernelGGL((finalize_kernel<TM, false>), grid, dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((finalize_kernel<TM, 0>), grid, dim3(256), 0, stream, a);
 }
 
 void launch_finalize(const SearchArgs &a, hipStream_t stream) {
@@ -153,7 +157,7 @@ kbm_status check_search(const kbm_stack *stacks, const kbm_search_params *p,
 //    epochs keep some lane inside the image);
 //  * ranks: nearest ranks floor(q (n-1) + 1/2) of q_lo, 1/2, q_hi, n = 0..64.
 void make_tables(const kbm_stack &s, const kbm_search_params &p,
-                 const StackLayout &l, std::vector<char> &buf) {
+                 const StackLayout &l, int split, std::vector<char> &buf) {
     const int T = s.num_epochs, V = p.num_vel;
     double t0 = s.times[0];
     for (int i = 1; i < T; ++i) t0 = std::min(t0, s.times[i]);
@@ -177,7 +181,8 @@ void make_tables(const kbm_stack &s, const kbm_search_params &p,
             const int cx = std::max(-32767, std::min(32767, dx));
             const int cy = std::max(-32767, std::min(32767, dy));
             off[(size_t)v * T + i] = (int)((uint32_t)(cx & 0xffff) | ((uint32_t)cy << 16));
-            const int64_t li = (int64_t)i * HW + (int64_t)cy * s.width + cx;
+            const int64_t li = (int64_t)(i < split ? i : i - split) * HW +
+                               (int64_t)cy * s.width + cx;
             lin[(size_t)v * T + i] = (uint32_t)(uint64_t)li;
             b.x = std::min(b.x, cx);
             b.y = std::max(b.y, cx);
@@ -262,7 +267,8 @@ extern "C" kbm_status kbm_search(const kbm_stack *stacks,
         const int Wr = q.x_end - q.x_begin, Hr = q.y_end - q.y_begin;
         if (Wr == 0 || Hr == 0) continue;
         char *ws = static_cast<char *>(workspace);
-        make_tables(s, q, l, tables);
+        const PlaneMode pm = plane_mode(s.num_epochs, (int64_t)s.width * s.height);
+        make_tables(s, q, l, pm.split, tables);
         st = stage_to_device(ws + l.tab_off, tables.data(), l.tab_bytes, stream);
         if (st != KBM_OK) return st;
         int *flags = reinterpret_cast<int *>(ws + l.flags_off);
@@ -278,10 +284,16 @@ extern "C" kbm_status kbm_search(const kbm_stack *stacks,
         SearchArgs a{};
         a.pk = pk;
         // One buffer descriptor covers every epoch plane when the packed
-        // planes fit 32-bit byte offsets (pk_bytes != 0); larger stacks read
-        // through 64-bit addresses.
-        a.pk_bytes = l.pk_bytes <= 0xffffffffull ? (uint32_t)l.pk_bytes : 0u;
-        a.n_elem = (uint32_t)n;
+        // planes fit 32-bit byte offsets; else two descriptors over two
+        // epoch groups; else 64-bit addresses.
+        const size_t hw = (size_t)s.width * s.height;
+        a.am = pm.am;
+        a.split = pm.split;
+        a.n_elem = (uint32_t)(pm.am == 2 ? (size_t)pm.split * hw : n);
+        a.pk_bytes = pm.am == 0 ? 0u : (uint32_t)(8 * (size_t)a.n_elem);
+        a.pk2 = pk + (pm.am == 2 ? (size_t)pm.split * hw : 0);
+        a.n_elem2 = (uint32_t)(pm.am == 2 ? n - (size_t)pm.split * hw : 0);
+        a.pk2_bytes = (uint32_t)(8 * (size_t)a.n_elem2);
         a.off16 = reinterpret_cast<const int *>(ws + l.tab_off + l.off_rel);
         a.lin = reinterpret_cast<const uint32_t *>(ws + l.tab_off + l.lin_rel);
         a.vbox = reinterpret_cast<const int4 *>(ws + l.tab_off + l.box_rel);

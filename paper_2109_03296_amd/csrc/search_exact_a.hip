@@ -5,10 +5,10 @@ namespace kbm {
 namespace srch {
 
 #define KBM_EXACT_CASE(n) \
-    case n: launch_chunks<n, 8, true, true>(a, stream); return true;
+    case n: launch_chunks<n, 8, true, 1>(a, stream); return true;
 
 bool launch_exact_a(int T, const SearchArgs &a, hipStream_t stream) {
-    if (a.K > 8 || a.pk_bytes == 0) return false;
+    if (a.K > 8 || a.am != 1) return false;
     switch (T) {
         KBM_EXACT_CASE(1) KBM_EXACT_CASE(2) KBM_EXACT_CASE(3) KBM_EXACT_CASE(4)
         KBM_EXACT_CASE(5) KBM_EXACT_CASE(6) KBM_EXACT_CASE(7) KBM_EXACT_CASE(8)

@@ -83,10 +83,20 @@ __device__ __forceinline__ int4 ld_box(const int4 *t, int i) {
     return make_int4(p[0], p[1], p[2], p[3]);
 }
 
+// Plane addressing modes (template parameter AM): 0 = 64-bit addresses;
+// 1 = one buffer descriptor over all epochs (packed planes below 4 GB);
+// 2 = two descriptors, epochs [0, split) and [split, T) with split = T/2,
+// each group below 4 GB, per-epoch element offsets relative to their group
+// (in exact-T code the group of every epoch is a compile-time constant).
 struct SearchArgs {
     const float2 *pk;         // [T][H][W] (nu, s)
-    uint32_t pk_bytes;        // bytes covered by the buffer descriptor
-    uint32_t n_elem;          // T H W
+    uint32_t pk_bytes;        // bytes covered by the (first) descriptor
+    uint32_t n_elem;          // elements of the first group (T H W if one)
+    const float2 *pk2;        // first element of epoch `split`
+    uint32_t pk2_bytes;       // bytes covered by the second descriptor
+    uint32_t n_elem2;         // elements of the second group
+    int split;                // epochs in the first group (T unless AM = 2)
+    int am;                   // addressing mode of this stack (0, 1, 2)
     const int *off16;         // [V][T] (dx & 0xffff) | (dy << 16)
     const uint32_t *lin;      // [V][T] i H W + dy W + dx (mod 2^32)
     const int4 *vbox;         // [V] (dxmin, dxmax, dymin, dymax)
@@ -113,10 +123,23 @@ __device__ __forceinline__ bool ranks_before(float la, int ia, float lb,
     return la > lb || (la == lb && ia < ib);
 }
 
+struct PlaneRsrc {
+    __amdgpu_buffer_rsrc_t r0, r1;  // epoch groups [0, split), [split, T)
+};
+
 template <class A>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const A &a) {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)a.pk, (short)0,
-                                             (int)a.pk_bytes, BUF_DWORD3);
+__device__ __forceinline__ PlaneRsrc plane_rsrc(const A &a) {
+    return PlaneRsrc{
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.pk, (short)0, (int)a.pk_bytes, BUF_DWORD3),
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.pk2, (short)0, (int)a.pk2_bytes,
+                                          BUF_DWORD3)};
+}
+
+// Whether epoch i (a compile-time index in the unrolled loops) lies in the
+// second group; SPLIT >= 0 is the split known at compile time (exact T).
+template <int AM, int SPLIT, class A>
+__device__ __forceinline__ bool second_group(const A &a, int i) {
+    return AM == 2 && (SPLIT >= 0 ? i >= SPLIT : i >= a.split);
 }
 
 __device__ __forceinline__ float2 ld_plane(__amdgpu_buffer_rsrc_t r,
@@ -127,11 +150,11 @@ __device__ __forceinline__ float2 ld_plane(__amdgpu_buffer_rsrc_t r,
 
 // Element e of the packed planes, clamped into the planes (an out-of-image
 // lane's offset may wrap; its value is discarded by the caller).
-template <bool SINGLE, class A>
-__device__ __forceinline__ float2 ld_elem(const A &a,
-                                          __amdgpu_buffer_rsrc_t r, uint32_t e) {
-    const uint32_t c = min(e, a.n_elem - 1u);
-    if (SINGLE) return ld_plane(r, c * 8u, 0u);
+template <int AM, int SPLIT, class A>
+__device__ __forceinline__ float2 ld_elem(const A &a, const PlaneRsrc &r, int i, uint32_t e) {
+    const bool g1 = second_group<AM, SPLIT>(a, i);
+    const uint32_t c = min(e, (g1 ? a.n_elem2 : a.n_elem) - 1u);
+    if (AM > 0) return ld_plane(g1 ? r.r1 : r.r0, c * 8u, 0u);
     return a.pk[c];
 }
 
@@ -225,9 +248,9 @@ __device__ __forceinline__ float score_fixed(const A &a,
 }
 
 // Whole-wave in-bounds load: the per-epoch offset is wave-uniform.
-template <int TM, bool CLEAN, bool EXACT, bool SINGLE, class A>
+template <int TM, bool CLEAN, bool EXACT, int AM, class A>
 __device__ __forceinline__ int load_fast(const A &a,
-                                         __amdgpu_buffer_rsrc_t rs,
+                                         const PlaneRsrc &rs,
                                          uint32_t lane, uint32_t wave_e,
                                          const KBM_CONST uint32_t *lv, float (&nu)[TM],
                                          float (&s)[TM]) {
@@ -237,7 +260,9 @@ __device__ __forceinline__ int load_fast(const A &a,
     for (int i = 0; i < TM; ++i) {
         if (i < T) {
             const uint32_t e = wave_e + lv[i];
-            const float2 q = SINGLE ? ld_plane(rs, lane * 8u, e * 8u)
+            const float2 q = AM > 0 ? ld_plane(second_group<AM, EXACT ? TM / 2 : -1>(a, i)
+                                                   ? rs.r1 : rs.r0,
+                                               lane * 8u, e * 8u)
                                     : a.pk[(size_t)e + lane];
             nu[i] = q.x;
             s[i] = q.y;
@@ -251,9 +276,9 @@ __device__ __forceinline__ int load_fast(const A &a,
 }
 
 // General load with per-lane bounds checks.
-template <int TM, bool EXACT, bool SINGLE, class A>
+template <int TM, bool EXACT, int AM, class A>
 __device__ __forceinline__ int load_slow(const A &a,
-                                         __amdgpu_buffer_rsrc_t rs, int x,
+                                         const PlaneRsrc &rs, int x,
                                          int y, const KBM_CONST int *ov,
                                          const KBM_CONST uint32_t *lv, float (&nu)[TM],
                                          float (&s)[TM]) {
@@ -267,7 +292,7 @@ __device__ __forceinline__ int load_slow(const A &a,
             const int dx = (int)(int16_t)(o & 0xffff), dy = o >> 16;
             const bool inb = (unsigned)(x + dx) < (unsigned)a.W &&
                              (unsigned)(y + dy) < (unsigned)a.H;
-            const float2 q = ld_elem<SINGLE>(a, rs, lv[i] + pix);
+            const float2 q = ld_elem<AM, EXACT ? TM / 2 : -1>(a, rs, i, lv[i] + pix);
             const bool ok = inb && (q.x == q.x);
             nu[i] = ok ? q.x : __builtin_nanf("");
             s[i] = ok ? q.y : 0.0f;
@@ -299,7 +324,7 @@ __device__ __forceinline__ bool map_tile(const SearchArgs &a, int &tx, int &ty) 
 // first set the running lists start empty, else they are read from the
 // workspace; they are written back at the end.  mL/mI point to an LDS block
 // of (NW-1)*KM*WAVE entries each (unused when NW == 1).
-template <int TM, int KM, bool CLEAN, bool EXACT, bool SINGLE, int NWT = NW, class A>
+template <int TM, int KM, bool CLEAN, bool EXACT, int AM, int NWT = NW, class A>
 __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
                                           int v_begin, int v_end, bool first,
                                           float *mL, int *mI) {
@@ -316,7 +341,7 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     const size_t npix = (size_t)a.Wr * a.Hr;
     const size_t pix = (size_t)ry * a.Wr + (active ? rx : 0);
     const int T = EXACT ? TM : a.T;
-    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(a);
+    const PlaneRsrc rs = plane_rsrc(a);
 
     float kL[KM];
     int kI[KM];
@@ -355,14 +380,14 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         int nv;
         Score sc;
         if (fast) {
-            nv = load_fast<TM, CLEAN, EXACT, SINGLE>(a, rs, lane, wave_e,
+            nv = load_fast<TM, CLEAN, EXACT, AM>(a, rs, lane, wave_e,
                                                      cst(a.lin) + (size_t)v * T, nu, s);
             if (EXACT && CLEAN && a.defq)
                 sc.L = score_fixed<TM>(a, nu, s);
             else
                 sc = score<TM, !CLEAN, EXACT>(a, nu, s, nv);
         } else {
-            nv = load_slow<TM, EXACT, SINGLE>(a, rs, x, y, cst(a.off16) + (size_t)v * T,
+            nv = load_slow<TM, EXACT, AM>(a, rs, x, y, cst(a.off16) + (size_t)v * T,
                                               cst(a.lin) + (size_t)v * T, nu, s);
             sc = score<TM, true, EXACT>(a, nu, s, nv);
         }
@@ -448,7 +473,7 @@ __device__ __forceinline__ void topk_insert(float (&kL)[KM], int (&kI)[KM],
     }
 }
 
-template <int TM, int KM, bool EXACT, bool SINGLE>
+template <int TM, int KM, bool EXACT, int AM>
 __global__ __launch_bounds__(WAVE * NW)
 __attribute__((amdgpu_waves_per_eu(1, KBM_MAX_WAVES_PER_SIMD)))
 void search_chunk_kernel(SearchArgs a) {
@@ -457,16 +482,16 @@ void search_chunk_kernel(SearchArgs a) {
     int tx, ty;
     if (!map_tile(a, tx, ty)) return;
     if (cst(a.flags)[0] == 0)
-        run_chunk<TM, KM, true, EXACT, SINGLE>(a, tx, ty, a.v_begin, a.v_end, a.first, mL, mI);
+        run_chunk<TM, KM, true, EXACT, AM>(a, tx, ty, a.v_begin, a.v_end, a.first, mL, mI);
     else
-        run_chunk<TM, KM, false, EXACT, SINGLE>(a, tx, ty, a.v_begin, a.v_end, a.first, mL, mI);
+        run_chunk<TM, KM, false, EXACT, AM>(a, tx, ty, a.v_begin, a.v_end, a.first, mL, mI);
 }
 
 // Re-evaluate the K winners of start pixel (x, y) (flat result index pix
 // within the region) from the running lists and write all result fields.
-template <int TM, bool EXACT, bool SINGLE, class A>
+template <int TM, bool EXACT, int AM, class A>
 __device__ __forceinline__ void finalize_pixel(const A &a,
-                                               __amdgpu_buffer_rsrc_t rs, int x,
+                                               const PlaneRsrc &rs, int x,
                                                int y, size_t pix) {
     const size_t npix = (size_t)a.Wr * a.Hr;
     const int T = EXACT ? TM : a.T;
@@ -483,7 +508,7 @@ __device__ __forceinline__ void finalize_pixel(const A &a,
             continue;
         }
         float nu[TM], s[TM];
-        const int nv = load_slow<TM, EXACT, SINGLE>(a, rs, x, y, cst(a.off16) + (size_t)vi * T,
+        const int nv = load_slow<TM, EXACT, AM>(a, rs, x, y, cst(a.off16) + (size_t)vi * T,
                                                     cst(a.lin) + (size_t)vi * T, nu, s);
         const Score sc = score<TM, true, EXACT>(a, nu, s, nv);
         a.lh[o] = sc.L;
@@ -505,23 +530,23 @@ __device__ __forceinline__ void finalize_pixel(const A &a,
     }
 }
 
-template <int TM, bool SINGLE>
+template <int TM, int AM>
 __global__ __launch_bounds__(256) void finalize_kernel(SearchArgs a) {
     const size_t npix = (size_t)a.Wr * a.Hr;
     const size_t pix = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= npix) return;
     const int rx = (int)(pix % a.Wr), ry = (int)(pix / a.Wr);
-    finalize_pixel<TM, false, SINGLE>(a, plane_rsrc(a), a.x0 + rx, a.y0 + ry, pix);
+    finalize_pixel<TM, false, AM>(a, plane_rsrc(a), a.x0 + rx, a.y0 + ry, pix);
 }
 
 // Launch the chunk sequence for one kernel variant.
-template <int TM, int KM, bool EXACT, bool SINGLE>
+template <int TM, int KM, bool EXACT, int AM>
 void launch_chunks(SearchArgs a, hipStream_t stream) {
     for (int v0 = 0; v0 < a.V; v0 += VCHUNK) {
         a.v_begin = v0;
         a.v_end = v0 + VCHUNK < a.V ? v0 + VCHUNK : a.V;
         a.first = v0 == 0;
-        hipLaunchKernelGGL((search_chunk_kernel<TM, KM, EXACT, SINGLE>), dim3(a.n_tiles),
+        hipLaunchKernelGGL((search_chunk_kernel<TM, KM, EXACT, AM>), dim3(a.n_tiles),
                            dim3(WAVE * NW), 0, stream, a);
     }
 }

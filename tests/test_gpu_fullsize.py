@@ -7,6 +7,10 @@
   injected source's start, random pixels, image corners and edges) are
   re-searched by the oracle one pixel at a time; properties that hold at
   every pixel are checked on the whole result.
+* The full-pipeline stack (4096 x 4096, T = 60 over 5 nights, 64 x 64
+  velocities): its packed planes (8 GB) exceed one 32-bit buffer
+  descriptor, so the search reads them through two; sampled pixels against
+  the oracle.
 * The batched recipe (62 stacks, sides drawn independently, T in [10, 30],
   PSF sigma in [1, 2], 64 x 64 velocities, K = 8) at reduced image sides:
   the persistent kernel against the per-stack search (bit-identical) and,
@@ -124,6 +128,29 @@ def test_fullsize_c2_sampled_pixels(oracle_mod, c2):
 def test_fullsize_c2_properties(c2):
     st, psi, phi, p, g = c2
     _properties(g, st.T, len(st.vels), p["min_obs"])
+
+
+def test_fullsize_c5_sampled_pixels(kbm, oracle_mod):
+    _say("full size: generating the full-pipeline stack")
+    st = synth.make_config(5)
+    _say("full size: oracle planes (T = 60)")
+    psi, phi = oracle_mod.planes(st.sci, st.var, st.mask, st.psf)
+    psi, phi = psi.astype(np.float32), phi.astype(np.float32)
+    p = dict(st.params)
+    sp = kbm.SearchParams(k=p["k"], min_obs=p["min_obs"], sigmag=True)
+    gpsi, gphi = torch.from_numpy(psi).cuda(), torch.from_numpy(phi).cuda()
+    _say("full size: search (two plane descriptors)")
+    g = _np(kbm.search(gpsi, gphi, st.times, st.vels, sp))
+    del gpsi, gphi
+    torch.cuda.empty_cache()
+    T, H, W = st.sci.shape
+    rng = np.random.default_rng(17)
+    pix = {(int(round(s["x0"])), int(round(s["y0"]))) for s in st.sources[:40]}
+    pix |= {(int(x), int(y)) for x, y in zip(rng.integers(0, W, 40), rng.integers(0, H, 40))}
+    pix |= {(0, 0), (W - 1, H - 1), (W // 2, H // 2), (W - 1, 0), (0, H - 1)}
+    _say(f"full size: oracle on {len(pix)} sampled pixels")
+    _pixel_check(oracle_mod, psi, phi, st, p, g, sorted(pix))
+    _properties(g, T, len(st.vels), p["min_obs"])
 
 
 def test_c3_recipe_batch(kbm, oracle_mod):
