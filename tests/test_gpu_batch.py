@@ -149,6 +149,22 @@ def test_batch_schedules_identical(kbm, batch, sched):
         _equal(r, b["plain"])
 
 
+def test_batch_up_to_27_epochs(kbm, batch):
+    """A batch of the shorter stacks only, under the default and an explicit
+    schedule."""
+    _say("batch: stacks with T <= 27 only")
+    sub = [b for b in batch if b["st"].T <= 27]
+    assert len(sub) >= 4
+    for sched in (None, dict(vel_block=64, tile_cols=2, tile_rows=32, waves=4,
+                             blocks_per_cu=0)):
+        with kbm.BatchedSearch([b["item"] for b in sub],
+                               tune=kbm.TUNE_DEFAULT if sched is None else sched) as plan:
+            plan.run()
+            assert not plan.check()
+            for b, r in zip(sub, plan.results):
+                _equal(r, b["plain"])
+
+
 def test_batch_graph_replay_and_refill(kbm, batch):
     _say("batch: graph replays and refilled planes")
     items = [dict(b["item"], psi=b["item"]["psi"].clone(), phi=b["item"]["phi"].clone())
