@@ -12,6 +12,7 @@ follows).  This module builds it with gcc and marshals numpy arrays.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 import threading
@@ -231,3 +232,88 @@ def adam_step(p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8,
     vh = v / (1.0 - beta2 ** step)
     p = p - np.asarray(lr, np.float64) * mh / (np.sqrt(vh) + eps)
     return p, m, v
+
+
+STAMP_LIMITS = (0.5, 0.5, 1.5, 36.5, 36.5)   # |x|, |y|, |xy|, xx, yy (Section 3.3)
+
+
+def stamps(sci, var, mask, times, params, radius=10, keep=None):
+    """Median coadded postage stamps along trajectories (Section 3.3):
+    for each trajectory (params [n][4] = x0, y0, vx, vy, float32) and epoch
+    i, the (2r+1)^2 window of the science image centred on the pixel
+    (floor(x0 + vx t_i + 1/2), floor(y0 + vy t_i + 1/2)); a pixel of an epoch
+    is usable when it lies in the image, is unmasked, and sci, var are
+    finite with var > 0 (and, with ``keep`` given, the epoch's keep bit is
+    set).  The coadd is numpy's median of the usable values of each stamp
+    pixel (mean of the two middle values for an even count), 0 where none is
+    usable.  Returns float32 [n][2r+1][2r+1]."""
+    sci = np.asarray(sci, np.float32)
+    var = np.asarray(var, np.float32)
+    T, H, W = sci.shape
+    times = np.asarray(times, np.float64)
+    t = times - times.min()
+    params = np.asarray(params, np.float32).reshape(-1, 4)
+    n = params.shape[0]
+    k = 2 * radius + 1
+    ok_pix = np.isfinite(sci) & np.isfinite(var) & (var > 0)
+    if mask is not None:
+        ok_pix &= np.asarray(mask) == 0
+    out = np.zeros((n, k, k), np.float32)
+    d = np.arange(-radius, radius + 1)
+    for j in range(n):
+        x0, y0, vx, vy = (float(v) for v in params[j])
+        cube = np.full((T, k, k), np.nan, np.float32)
+        for i in range(T):
+            if keep is not None and not (int(keep[j]) >> i) & 1:
+                continue
+            cx = math.floor(x0 + vx * t[i] + 0.5)
+            cy = math.floor(y0 + vy * t[i] + 0.5)
+            ys, xs = cy + d, cx + d
+            iny = (ys >= 0) & (ys < H)
+            inx = (xs >= 0) & (xs < W)
+            sub = np.full((k, k), np.nan, np.float32)
+            yy, xx = np.ix_(np.where(iny)[0], np.where(inx)[0])
+            src_y, src_x = np.ix_(ys[iny], xs[inx])
+            vals = sci[i][src_y, src_x]
+            good = ok_pix[i][src_y, src_x]
+            sub[yy, xx] = np.where(good, vals, np.nan)
+            cube[i] = sub
+        with np.errstate(all="ignore"):
+            import warnings
+            with warnings.catch_warnings():
+                warnings.simplefilter("ignore", RuntimeWarning)
+                med = np.nanmedian(cube, axis=0)
+        out[j] = np.where(np.isnan(med), np.float32(0), med).astype(np.float32)
+    return out
+
+
+def stamp_moments(stamp):
+    """Central moments of a coadded stamp (Section 3.3) in FP64: with
+    S normalised to unit sum and offsets dx, dy from the centre pixel,
+    (sum, x, y, xy, xx, yy) = (sum S, sum dx S, sum dy S, sum dx dy S,
+    sum dx^2 S, sum dy^2 S).  A stamp whose sum is not positive gets NaN
+    moments."""
+    s = np.asarray(stamp, np.float64)
+    k = s.shape[-1]
+    r = k // 2
+    d = np.arange(-r, r + 1, dtype=np.float64)
+    tot = s.sum(axis=(-1, -2))
+    with np.errstate(all="ignore"):
+        w = s / tot[..., None, None]
+    dx = d[None, :]
+    dy = d[:, None]
+    m = np.stack([tot, (w * dx).sum((-1, -2)), (w * dy).sum((-1, -2)),
+                  (w * dx * dy).sum((-1, -2)), (w * dx * dx).sum((-1, -2)),
+                  (w * dy * dy).sum((-1, -2))], -1)
+    m[..., 1:] = np.where((tot > 0)[..., None], m[..., 1:], np.nan)
+    return m
+
+
+def stamp_pass(moments, limits=STAMP_LIMITS):
+    """The central-moment cut of Section 3.3: |x|, |y|, |xy| and xx, yy all
+    strictly below their limits (NaN moments fail)."""
+    m = np.asarray(moments, np.float64)
+    lx, ly, lxy, lxx, lyy = limits
+    with np.errstate(invalid="ignore"):
+        return ((np.abs(m[..., 1]) < lx) & (np.abs(m[..., 2]) < ly) &
+                (np.abs(m[..., 3]) < lxy) & (m[..., 4] < lxx) & (m[..., 5] < lyy))
