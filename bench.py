@@ -102,7 +102,7 @@ def cpu_baseline(st, params, log_fn):
     vx_max = float(np.max(np.abs(st.vels[:, 0]))) * float(st.times.max())
     vy_max = float(np.max(np.abs(st.vels[:, 1]))) * float(st.times.max())
     r = st.psf.shape[0] // 2
-    bx = by = 48
+    bx = by = 112   # about 10 s of oracle work on a 16-core host
     wx = min(W, int(bx + vx_max + 2 * r + 4))
     wy = min(H, int(by + 2 * vy_max + 2 * r + 4))
     y0 = max(0, H // 2 - wy // 2)

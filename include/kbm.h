@@ -296,6 +296,37 @@ kbm_status kbm_score_trajectories(const kbm_stack *s, const float *psi,
                                   float *lh_raw, hipStream_t stream);
 
 /*
+ * kbm_stamps - median coadded postage stamps along trajectories and the
+ * central-moment cut of Section 3.3.
+ *
+ * For trajectory j (params x0, y0, vx, vy) and epoch i, the stamp is the
+ * (2r+1) x (2r+1) window of the science image centred on the pixel
+ * (floor((x0 + vx t_i) + 1/2), floor((y0 + vy t_i) + 1/2)) (FP64, as in
+ * kbm_score_trajectories).  A stamp pixel of an epoch is usable when it lies
+ * in the image, is unmasked, sci and var are finite and var > 0, and (with
+ * `keep` given) bit i of keep[j] is set.  The coadd pixel is the median of
+ * its usable values (the mean of the two middle values for an even count,
+ * in binary32), 0 if none.  With S the coadd, offsets dx, dy from its centre
+ * pixel and sums in FP64: moments = (sum S, x, y, xy, xx, yy) with
+ * x = sum dx S / sum S, ..., yy = sum dy^2 S / sum S (NaN if sum S <= 0).
+ * pass = |x| < lim[0] && |y| < lim[1] && |xy| < lim[2] && xx < lim[3] &&
+ * yy < lim[4] (strict; the paper's limits 0.5, 0.5, 1.5, 36.5, 36.5).
+ *
+ *   sci, var : device float [T][H][W]; mask: device uint8 [T][H][W] or NULL
+ *   params   : device float [n][4], 16-byte aligned
+ *   keep     : device uint64 [n] or NULL (all epochs)
+ *   radius   : r in [1, 15] (the paper's stamps are 21 x 21: r = 10)
+ *   limits   : host double [5], or NULL for the paper's
+ *   coadd    : device float [n][2r+1][2r+1] or NULL
+ *   moments  : device double [n][6]; pass: device uint8 [n]
+ */
+kbm_status kbm_stamps(const kbm_stack *s, const float *sci, const float *var,
+                      const uint8_t *mask, int64_t n, const float *params,
+                      const uint64_t *keep, int32_t radius,
+                      const double *limits, float *coadd, double *moments,
+                      uint8_t *pass, hipStream_t stream);
+
+/*
  * kbm_extract_top - candidate extraction: the global top-N result slots by
  * filtered likelihood with L' >= lh_min (the paper hands trajectories whose
  * recomputed likelihood clears a threshold on from the GPU, Section 3.1, and

@@ -28,7 +28,7 @@ __all__ = [
     "refine_backward", "TrajLH", "SearchParams", "MAX_EPOCHS", "MAX_K",
     "MAX_PSF", "extract_top", "adam_step", "refine", "BatchedSearch",
     "Schedule", "batch_workspace_size", "extract_workspace_size",
-    "score_trajectories",
+    "score_trajectories", "stamps", "STAMP_LIMITS",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -102,6 +102,7 @@ def lib():
         L.kbm_batch_destroy.argtypes = [P]
         L.kbm_score_trajectories.argtypes = [P, P, P, i64, P, i32, i32, f64, f64,
                                              f64, f64, P, P, P, P, P, P]
+        L.kbm_stamps.argtypes = [P, P, P, P, i64, P, P, i32, P, P, P, P, P]
         _lib = L
         return L
 
@@ -549,6 +550,38 @@ def score_trajectories(psi, phi, times, params, params_search: Optional[SearchPa
         float(p.n_sigma), _ptr(out["lh"]), _ptr(out["flux"]), _ptr(out["keep"]),
         _ptr(out["n_obs"]), _ptr(out["lh_raw"]), _stream(stream)))
     return out
+
+
+STAMP_LIMITS = (0.5, 0.5, 1.5, 36.5, 36.5)
+
+
+def stamps(sci, var, mask, times, params, keep=None, radius=10, limits=None,
+           want_coadd=True, stream=None):
+    """Median coadded stamps along trajectories ``params`` [n][4] and the
+    central-moment cut (Section 3.3).  Returns a dict: coadd [n][2r+1][2r+1]
+    (or None), moments float64 [n][6] (sum, x, y, xy, xx, yy), pass bool [n]."""
+    T, H, W = sci.shape
+    _dev(sci, torch.float32, "sci")
+    _dev(var, torch.float32, "var", sci.shape)
+    if mask is not None:
+        _dev(mask, torch.uint8, "mask", sci.shape)
+    prm = _dev(params, torch.float32, "params")
+    if prm.dim() != 2 or prm.shape[1] != 4:
+        raise ValueError("params must be [n][4]")
+    if keep is not None:
+        _dev(keep, torch.int64, "keep", (prm.shape[0],))
+    n = prm.shape[0]
+    k = 2 * int(radius) + 1
+    st, _t = _stack(T, H, W, times)
+    dev = sci.device
+    coadd = torch.empty((n, k, k), dtype=torch.float32, device=dev) if want_coadd else None
+    moments = torch.empty((n, 6), dtype=torch.float64, device=dev)
+    ok = torch.empty(n, dtype=torch.uint8, device=dev)
+    lim = None if limits is None else (C.c_double * 5)(*[float(v) for v in limits])
+    _check("kbm_stamps", lib().kbm_stamps(
+        C.byref(st), _ptr(sci), _ptr(var), _ptr(mask), n, _ptr(prm), _ptr(keep),
+        int(radius), lim, _ptr(coadd), _ptr(moments), _ptr(ok), _stream(stream)))
+    return dict(coadd=coadd, moments=moments, passed=ok.bool())
 
 
 def extract_workspace_size(Hr, Wr, k, num_vel) -> int:

@@ -200,6 +200,21 @@ def test_score_validation(L):
                                     0.7413, 2.0, FAKE, FAKE, FAKE, FAKE, None, None) == 1
 
 
+def test_stamps_validation(L):
+    st, t = _stack()
+    a = lambda n, r=10, lim=None: (C.byref(st), FAKE, FAKE, None, n, FAKE, None, r, lim,
+                                   None, FAKE, FAKE, None)
+    assert L.kbm_stamps(*a(-1)) == 1
+    assert L.kbm_stamps(*a(3, r=0)) == 1
+    assert L.kbm_stamps(*a(3, r=16)) == 1
+    bad = (C.c_double * 5)(0.5, float("nan"), 1.5, 36.5, 36.5)
+    assert L.kbm_stamps(*a(3, lim=bad)) == 1
+    assert L.kbm_stamps(*a(0)) == 0
+    odd = C.c_void_p(0x1004)   # params must be 16-byte aligned
+    assert L.kbm_stamps(C.byref(st), FAKE, FAKE, None, 3, odd, None, 10, None, None,
+                        FAKE, FAKE, None) == 1
+
+
 def test_binding_rejects_host_tensors():
     import torch
     import paper_2109_03296_amd as kbm
