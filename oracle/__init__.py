@@ -53,6 +53,8 @@ def _load():
         lib.kbmo_offsets.argtypes = [i32, P, i32, P, P]
         lib.kbmo_offsets.restype = None
         lib.kbmo_sigmag.argtypes = [i64, i32, P, P, P, f64, f64, f64, f64, P, P]
+        lib.kbmo_sigmag_q.argtypes = [i64, i32, P, P, P, i32, f64, f64, f64, f64,
+                                      P, P]
         lib.kbmo_search.argtypes = [i32, i32, i32, P, P, P, i32, P, i32, i32,
                                     i32, f64, f64, f64, f64, i32, i32, i32,
                                     i32, P, P, P, P, P, P]
@@ -106,8 +108,9 @@ def offsets(times, vels):
 
 
 def sigmag(psi_curve, phi_curve=None, valid=None, q_lo=0.25, q_hi=0.75,
-           coeff=0.7413, n_sigma=2.0):
-    """Standalone sigma_G filter over ``[n][T]`` lightcurves.
+           coeff=0.7413, n_sigma=2.0, quantity=0):
+    """Standalone sigma_G filter over ``[n][T]`` lightcurves (Section 3.1);
+    ``quantity`` 0 filters psi/sqrt(phi) (likelihood), 1 psi/phi (flux).
 
     Returns (keep uint64 [n], lh float64 [n])."""
     lib = _load()
@@ -117,8 +120,8 @@ def sigmag(psi_curve, phi_curve=None, valid=None, q_lo=0.25, q_hi=0.75,
     va = _c(valid, np.uint8)
     keep = np.empty(n, np.uint64)
     lh = np.empty(n, np.float64)
-    rc = lib.kbmo_sigmag(n, T, _p(ps), _p(ph), _p(va), q_lo, q_hi, coeff,
-                         n_sigma, _p(keep), _p(lh))
+    rc = lib.kbmo_sigmag_q(n, T, _p(ps), _p(ph), _p(va), int(quantity), q_lo,
+                           q_hi, coeff, n_sigma, _p(keep), _p(lh))
     if rc:
         raise ValueError("oracle sigmag: bad arguments")
     return keep, lh
@@ -235,6 +238,14 @@ def adam_step(p, g, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8,
 
 
 STAMP_LIMITS = (0.5, 0.5, 1.5, 36.5, 36.5)   # |x|, |y|, |xy|, xx, yy (Section 3.3)
+
+
+def sigmag_coeff(q_lo, q_hi):
+    """C of Eq. 3 for a quantile pair: 1 / (sqrt(2) (erfinv(2 q_hi - 1) -
+    erfinv(2 q_lo - 1))), so that C (x_hi - x_lo) estimates sigma for normal
+    data (0.7413 for the 25th/75th percentiles, Section 3.1)."""
+    from scipy.special import erfinv
+    return 1.0 / (math.sqrt(2.0) * (erfinv(2.0 * q_hi - 1.0) - erfinv(2.0 * q_lo - 1.0)))
 
 
 def stamps(sci, var, mask, times, params, radius=10, keep=None):

@@ -136,6 +136,7 @@ void kbmo_offsets(int32_t T, const double *times, int32_t V, const float *vel,
 
 typedef struct {
     double q_lo, q_hi, coeff, n_sigma;
+    int quantity; /* filtered value per epoch: 0 psi/sqrt(phi), 1 psi/phi */
 } sg_params;
 
 /* Nearest-rank selection: the q-quantile of n sorted values is the value
@@ -160,7 +161,7 @@ static uint64_t sigmag_keep(int T, const float *ps, const float *ph,
     int n = 0;
     for (int i = 0; i < T; ++i) {
         if (!part[i]) continue;
-        nu[i] = ps[i] / sqrtf(ph[i]);
+        nu[i] = p->quantity ? ps[i] / ph[i] : ps[i] / sqrtf(ph[i]);
         s[n++] = nu[i];
     }
     if (n == 0) return 0;
@@ -181,15 +182,18 @@ static int usable(float ps, float ph)
     return ph > 0.0f && isfinite(ph) && isfinite(ps);
 }
 
-/* Standalone filter over n lightcurves [n][T].  phi == NULL means unit
- * weights (the values in psi are filtered directly).  lh = Psi'/sqrt(Phi')
- * over the kept epochs, -inf when nothing participates. */
-int kbmo_sigmag(int64_t n, int32_t T, const float *psi, const float *phi,
-                const uint8_t *valid, double q_lo, double q_hi, double coeff,
-                double n_sigma, uint64_t *keep, double *lh)
+/* Standalone filter over n lightcurves [n][T] (Section 3.1).  phi == NULL
+ * means unit weights (the values in psi are filtered directly).  The
+ * filtered per-epoch value is psi/sqrt(phi) (quantity 0, the likelihood) or
+ * psi/phi (quantity 1, the flux).  lh = Psi'/sqrt(Phi') over the kept
+ * epochs, -inf when nothing participates. */
+int kbmo_sigmag_q(int64_t n, int32_t T, const float *psi, const float *phi,
+                  const uint8_t *valid, int32_t quantity, double q_lo,
+                  double q_hi, double coeff, double n_sigma, uint64_t *keep,
+                  double *lh)
 {
-    if (T <= 0 || T > KBMO_MAX_T) return 1;
-    const sg_params p = {q_lo, q_hi, coeff, n_sigma};
+    if (T <= 0 || T > KBMO_MAX_T || (quantity != 0 && quantity != 1)) return 1;
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma, quantity};
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
         float ps[KBMO_MAX_T], ph[KBMO_MAX_T];
@@ -210,6 +214,14 @@ int kbmo_sigmag(int64_t n, int32_t T, const float *psi, const float *phi,
         if (lh) lh[c] = sf > 0.0 ? sp / sqrt(sf) : -INFINITY;
     }
     return 0;
+}
+
+int kbmo_sigmag(int64_t n, int32_t T, const float *psi, const float *phi,
+                const uint8_t *valid, double q_lo, double q_hi, double coeff,
+                double n_sigma, uint64_t *keep, double *lh)
+{
+    return kbmo_sigmag_q(n, T, psi, phi, valid, 0, q_lo, q_hi, coeff, n_sigma,
+                         keep, lh);
 }
 
 /* ------------------------------------------------------------------ */
@@ -237,7 +249,7 @@ int kbmo_search(int32_t T, int32_t H, int32_t W, const float *psi,
     int32_t *off = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)V * T);
     if (!off) return 3;
     kbmo_offsets(T, times, V, vel, off);
-    const sg_params p = {q_lo, q_hi, coeff, n_sigma};
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma, 0};
     const size_t plane = (size_t)H * W;
 
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
@@ -341,7 +353,7 @@ int kbmo_score(int32_t T, int32_t H, int32_t W, const float *psi,
                int32_t *out_nobs, double *out_lh_raw)
 {
     if (T <= 0 || T > KBMO_MAX_T || n < 0) return 1;
-    const sg_params p = {q_lo, q_hi, coeff, n_sigma};
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma, 0};
     const double t0 = earliest(T, times);
     const size_t plane = (size_t)H * W;
 
