@@ -242,6 +242,33 @@ kbm_status kbm_sigmag_filter(const float *psi_curve, const float *phi_curve,
                              float *lh_filtered, hipStream_t stream);
 
 /*
+ * kbm_sigmag_filter_ex - kbm_sigmag_filter with the variants Section 3.1
+ * leaves to the user: the filtered per-epoch value is psi/sqrt(phi)
+ * (quantity 0, the likelihood; what kbm_sigmag_filter and the search use)
+ * or psi/phi (quantity 1, the flux); and a post-filter flag
+ * pass = (L' >= lh_min) (the paper keeps trajectories whose recomputed
+ * likelihood clears a threshold, 10 in its searches).
+ *
+ *   pass : device uint8 [n] or NULL; 0 for curves with no usable epoch
+ * Other arguments as kbm_sigmag_filter; lh_min may be -inf, not NaN.
+ */
+kbm_status kbm_sigmag_filter_ex(const float *psi_curve, const float *phi_curve,
+                                const uint8_t *valid, int64_t n, int32_t T,
+                                int32_t quantity, double q_lo, double q_hi,
+                                double coeff, double n_sigma, double lh_min,
+                                uint64_t *keep, float *lh_filtered,
+                                uint8_t *pass, hipStream_t stream);
+
+/*
+ * kbm_sigmag_coeff - the constant C of Eq. 3 for a quantile pair, with the
+ * sqrt(2) that Eq. 4 as printed drops: C = 1 / (sqrt(2) (erfinv(2 q_hi - 1)
+ * - erfinv(2 q_lo - 1))), so C (x_hi - x_lo) estimates sigma for normal
+ * data (0.741301... for 0.25, 0.75; the paper prints 0.7413).  Host only,
+ * FP64; needs 0 < q_lo < q_hi < 1.
+ */
+kbm_status kbm_sigmag_coeff(double q_lo, double q_hi, double *coeff);
+
+/*
  * kbm_refine - bilinear trajectory likelihood and its adjoint, used to
  * refine candidates to sub-pixel start positions and velocities.  (Not a
  * step of the paper; it continues Section 3's likelihood to real-valued

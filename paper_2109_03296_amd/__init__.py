@@ -28,7 +28,7 @@ __all__ = [
     "refine_backward", "TrajLH", "SearchParams", "MAX_EPOCHS", "MAX_K",
     "MAX_PSF", "extract_top", "adam_step", "refine", "BatchedSearch",
     "Schedule", "batch_workspace_size", "extract_workspace_size",
-    "score_trajectories", "stamps", "STAMP_LIMITS",
+    "score_trajectories", "stamps", "STAMP_LIMITS", "sigmag_filter_ex", "sigmag_coeff",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -103,6 +103,9 @@ def lib():
         L.kbm_score_trajectories.argtypes = [P, P, P, i64, P, i32, i32, f64, f64,
                                              f64, f64, P, P, P, P, P, P]
         L.kbm_stamps.argtypes = [P, P, P, P, i64, P, P, i32, P, P, P, P, P]
+        L.kbm_sigmag_filter_ex.argtypes = [P, P, P, i64, i32, i32, f64, f64, f64, f64,
+                                           f64, P, P, P, P]
+        L.kbm_sigmag_coeff.argtypes = [f64, f64, P]
         _lib = L
         return L
 
@@ -453,6 +456,39 @@ def sigmag_filter(psi_curve, phi_curve=None, valid=None, q_lo=0.25,
         _ptr(psi_curve), _ptr(phi_curve), _ptr(valid), n, T, q_lo, q_hi,
         coeff, n_sigma, _ptr(keep), _ptr(lh), _stream(stream)))
     return keep, lh
+
+
+def sigmag_filter_ex(psi_curve, phi_curve=None, valid=None, quantity=0, q_lo=0.25,
+                     q_hi=0.75, coeff=None, n_sigma=2.0, lh_min=float("-inf"),
+                     stream=None):
+    """sigma_G filter variants: ``quantity`` 0 filters psi/sqrt(phi), 1 the
+    flux psi/phi; ``coeff`` defaults to C of Eq. 3 for (q_lo, q_hi) (the
+    paper's 0.7413 for the quartiles).  Returns (keep, lh, pass) with pass =
+    lh >= lh_min."""
+    _dev(psi_curve, torch.float32, "psi_curve")
+    n, T = psi_curve.shape
+    if phi_curve is not None:
+        _dev(phi_curve, torch.float32, "phi_curve", psi_curve.shape)
+    if valid is not None:
+        _dev(valid, torch.uint8, "valid", psi_curve.shape)
+    if coeff is None:
+        coeff = 0.7413 if (q_lo, q_hi) == (0.25, 0.75) else sigmag_coeff(q_lo, q_hi)
+    dev = psi_curve.device
+    keep = torch.empty(n, dtype=torch.int64, device=dev)
+    lh = torch.empty(n, dtype=torch.float32, device=dev)
+    ok = torch.empty(n, dtype=torch.uint8, device=dev)
+    _check("kbm_sigmag_filter_ex", lib().kbm_sigmag_filter_ex(
+        _ptr(psi_curve), _ptr(phi_curve), _ptr(valid), n, T, int(quantity), q_lo, q_hi,
+        float(coeff), n_sigma, float(lh_min), _ptr(keep), _ptr(lh), _ptr(ok),
+        _stream(stream)))
+    return keep, lh, ok.bool()
+
+
+def sigmag_coeff(q_lo, q_hi) -> float:
+    """C of Eq. 3 for a quantile pair (host computation in the library)."""
+    c = C.c_double(0.0)
+    _check("kbm_sigmag_coeff", lib().kbm_sigmag_coeff(float(q_lo), float(q_hi), C.byref(c)))
+    return float(c.value)
 
 
 def refine_forward(psi, phi, times, params, keep=None, stream=None):

@@ -112,7 +112,41 @@ kbm_status stage_to_device(void *dst, const void *src, size_t bytes,
 
 }  // namespace kbm
 
+namespace {
+
+// Inverse error function in double: Winitzki's closed-form approximation
+// (a = 0.147) as the start, refined by Newton steps on std::erf.
+double inverse_erf(double y) {
+    if (y == 0.0) return 0.0;
+    const double a = 0.147, pi = 3.14159265358979323846;
+    const double l = std::log((1.0 - y) * (1.0 + y));
+    const double b = 2.0 / (pi * a) + 0.5 * l;
+    double x = std::copysign(std::sqrt(std::sqrt(b * b - l / a) - b), y);
+    for (int it = 0; it < 6; ++it) {
+        const double f = std::erf(x) - y;
+        const double d = 2.0 / std::sqrt(pi) * std::exp(-x * x);
+        const double step = f / d;
+        x -= step;
+        if (std::fabs(step) <= 1e-17 * std::fabs(x)) break;
+    }
+    return x;
+}
+
+}  // namespace
+
 extern "C" {
+
+kbm_status kbm_sigmag_coeff(double q_lo, double q_hi, double *coeff) {
+    kbm::clear_error();
+    KBM_REQUIRE(coeff != nullptr, KBM_ERR_INVALID_ARG, "kbm_sigmag_coeff: coeff is NULL");
+    KBM_REQUIRE(std::isfinite(q_lo) && std::isfinite(q_hi) && q_lo > 0.0 && q_lo < q_hi &&
+                    q_hi < 1.0,
+                KBM_ERR_INVALID_ARG, "kbm_sigmag_coeff: need 0 < q_lo < q_hi < 1 (got %g, %g)",
+                q_lo, q_hi);
+    const double d = inverse_erf(2.0 * q_hi - 1.0) - inverse_erf(2.0 * q_lo - 1.0);
+    *coeff = 1.0 / (std::sqrt(2.0) * d);
+    return KBM_OK;
+}
 
 const char *kbm_status_string(kbm_status s) {
     switch (s) {

@@ -1,7 +1,10 @@
 // Standalone sigma_G lightcurve filter (Section 3.1, Eqs. 1-5) over n
 // independent lightcurves, one lane per lightcurve.  Same rule, ranks and
 // binary32 decision as the filter fused into the search kernel (the device
-// code is shared through kbm_internal.h).
+// code is shared through kbm_internal.h).  The filtered per-epoch value is
+// the likelihood psi/sqrt(phi) or, as a variant the paper allows, the flux
+// psi/phi; a post-filter flag marks curves whose recomputed likelihood
+// reaches a threshold.
 #include "kbm_internal.h"
 
 namespace kbm {
@@ -10,9 +13,9 @@ namespace {
 template <int TM>
 __global__ __launch_bounds__(256) void sigmag_kernel(
     const float *__restrict__ psi, const float *__restrict__ phi,
-    const uint8_t *__restrict__ valid, int64_t n, int T, RankTable rt,
-    float coeff, float n_sigma, uint64_t *__restrict__ keep,
-    float *__restrict__ lh) {
+    const uint8_t *__restrict__ valid, int64_t n, int T, int quantity, RankTable rt,
+    float coeff, float n_sigma, float lh_min, uint64_t *__restrict__ keep,
+    float *__restrict__ lh, uint8_t *__restrict__ pass) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
     float ps[TM], ph[TM], nu[TM];
@@ -31,7 +34,7 @@ __global__ __launch_bounds__(256) void sigmag_kernel(
             if (ok) {
                 ps[i] = a;
                 ph[i] = b;
-                nu[i] = a / sqrtf(b);
+                nu[i] = quantity ? a / b : a / sqrtf(b);
                 ++nv;
             }
         }
@@ -39,6 +42,7 @@ __global__ __launch_bounds__(256) void sigmag_kernel(
     if (nv == 0) {
         keep[c] = 0;
         if (lh) lh[c] = -INFINITY;
+        if (pass) pass[c] = 0;
         return;
     }
     const SigmaGCut cut = sigmag_cut<TM, true>(nu, rt.lo[nv], rt.md[nv], rt.hi[nv], coeff, n_sigma);
@@ -57,35 +61,40 @@ __global__ __launch_bounds__(256) void sigmag_kernel(
         }
     }
     keep[c] = (uint64_t)lo | ((uint64_t)hi << 32);
-    if (lh) lh[c] = P / sqrtf(F);
+    const float L = P / sqrtf(F);
+    if (lh) lh[c] = L;
+    if (pass) pass[c] = L >= lh_min ? 1 : 0;
 }
 
 template <int TM>
 void launch(const float *psi, const float *phi, const uint8_t *valid,
-            int64_t n, int T, const RankTable &rt, float coeff, float ns,
-            uint64_t *keep, float *lh, hipStream_t stream) {
+            int64_t n, int T, int quantity, const RankTable &rt, float coeff, float ns,
+            float lh_min, uint64_t *keep, float *lh, uint8_t *pass, hipStream_t stream) {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL((sigmag_kernel<TM>), dim3((unsigned)blocks), dim3(256),
-                       0, stream, psi, phi, valid, n, T, rt, coeff, ns, keep,
-                       lh);
+                       0, stream, psi, phi, valid, n, T, quantity, rt, coeff, ns, lh_min,
+                       keep, lh, pass);
 }
 
 }  // namespace
 }  // namespace kbm
 
-extern "C" kbm_status kbm_sigmag_filter(const float *psi_curve,
-                                        const float *phi_curve,
-                                        const uint8_t *valid, int64_t n,
-                                        int32_t T, double q_lo, double q_hi,
-                                        double coeff, double n_sigma,
-                                        uint64_t *keep, float *lh_filtered,
-                                        hipStream_t stream) {
+extern "C" kbm_status kbm_sigmag_filter_ex(const float *psi_curve, const float *phi_curve,
+                                           const uint8_t *valid, int64_t n, int32_t T,
+                                           int32_t quantity, double q_lo, double q_hi,
+                                           double coeff, double n_sigma, double lh_min,
+                                           uint64_t *keep, float *lh_filtered,
+                                           uint8_t *pass, hipStream_t stream) {
     using namespace kbm;
     clear_error();
     KBM_REQUIRE(n >= 0, KBM_ERR_INVALID_ARG,
                 "kbm_sigmag_filter: n = %lld must be >= 0", (long long)n);
     KBM_REQUIRE(T >= 1 && T <= KBM_MAX_EPOCHS, KBM_ERR_INVALID_ARG,
                 "kbm_sigmag_filter: T = %d not in [1, %d]", T, KBM_MAX_EPOCHS);
+    KBM_REQUIRE(quantity == 0 || quantity == 1, KBM_ERR_INVALID_ARG,
+                "kbm_sigmag_filter: quantity = %d must be 0 (likelihood) or 1 (flux)",
+                quantity);
+    KBM_REQUIRE(!std::isnan(lh_min), KBM_ERR_INVALID_ARG, "kbm_sigmag_filter: lh_min is NaN");
     kbm_status st = check_sigmag_params(q_lo, q_hi, coeff, n_sigma);
     if (st != KBM_OK) return st;
     KBM_REQUIRE(n == 0 || (psi_curve != nullptr && keep != nullptr),
@@ -95,13 +104,28 @@ extern "C" kbm_status kbm_sigmag_filter(const float *psi_curve,
                 "kbm_sigmag_filter: n = %lld too large", (long long)n);
     if (n == 0) return KBM_OK;
     const RankTable rt = make_rank_table(q_lo, q_hi);
-    const float c = (float)coeff, ns = (float)n_sigma;
-    if (T <= 8) launch<8>(psi_curve, phi_curve, valid, n, T, rt, c, ns, keep, lh_filtered, stream);
-    else if (T <= 16) launch<16>(psi_curve, phi_curve, valid, n, T, rt, c, ns, keep, lh_filtered, stream);
-    else if (T <= 24) launch<24>(psi_curve, phi_curve, valid, n, T, rt, c, ns, keep, lh_filtered, stream);
-    else if (T <= 32) launch<32>(psi_curve, phi_curve, valid, n, T, rt, c, ns, keep, lh_filtered, stream);
-    else if (T <= 48) launch<48>(psi_curve, phi_curve, valid, n, T, rt, c, ns, keep, lh_filtered, stream);
-    else launch<64>(psi_curve, phi_curve, valid, n, T, rt, c, ns, keep, lh_filtered, stream);
+    const float c = (float)coeff, ns = (float)n_sigma, lm = (float)lh_min;
+#define KBM_SG_LAUNCH(TM) \
+    launch<TM>(psi_curve, phi_curve, valid, n, T, quantity, rt, c, ns, lm, keep, lh_filtered, \
+               pass, stream)
+    if (T <= 8) KBM_SG_LAUNCH(8);
+    else if (T <= 16) KBM_SG_LAUNCH(16);
+    else if (T <= 24) KBM_SG_LAUNCH(24);
+    else if (T <= 32) KBM_SG_LAUNCH(32);
+    else if (T <= 48) KBM_SG_LAUNCH(48);
+    else KBM_SG_LAUNCH(64);
+#undef KBM_SG_LAUNCH
     KBM_LAUNCHED("sigmag_kernel");
     return KBM_OK;
+}
+
+extern "C" kbm_status kbm_sigmag_filter(const float *psi_curve,
+                                        const float *phi_curve,
+                                        const uint8_t *valid, int64_t n,
+                                        int32_t T, double q_lo, double q_hi,
+                                        double coeff, double n_sigma,
+                                        uint64_t *keep, float *lh_filtered,
+                                        hipStream_t stream) {
+    return kbm_sigmag_filter_ex(psi_curve, phi_curve, valid, n, T, 0, q_lo, q_hi, coeff,
+                                n_sigma, -INFINITY, keep, lh_filtered, nullptr, stream);
 }

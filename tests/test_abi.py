@@ -215,6 +215,23 @@ def test_stamps_validation(L):
                         FAKE, FAKE, None) == 1
 
 
+def test_sigmag_coeff_host(L):
+    """C of Eq. 3 computed by the library on the host (no GPU needed)
+    against scipy's normal quantiles."""
+    from scipy import stats
+    c = C.c_double(0.0)
+    for ql, qh in ((0.25, 0.75), (0.1, 0.9), (0.05, 0.6), (0.3, 0.99)):
+        assert L.kbm_sigmag_coeff(ql, qh, C.byref(c)) == 0
+        want = 1.0 / (stats.norm.ppf(qh) - stats.norm.ppf(ql))
+        assert c.value == pytest.approx(want, rel=1e-13)
+    for ql, qh in ((0.0, 0.75), (0.5, 0.5), (0.2, 1.0), (float("nan"), 0.7)):
+        assert L.kbm_sigmag_coeff(ql, qh, C.byref(c)) == 1
+    assert L.kbm_sigmag_filter_ex(FAKE, None, None, 10, 5, 2, 0.25, 0.75, 0.7413, 2.0,
+                                  0.0, FAKE, None, None, None) == 1
+    assert L.kbm_sigmag_filter_ex(FAKE, None, None, 10, 5, 0, 0.25, 0.75, 0.7413, 2.0,
+                                  float("nan"), FAKE, None, None, None) == 1
+
+
 def test_binding_rejects_host_tensors():
     import torch
     import paper_2109_03296_amd as kbm

@@ -271,3 +271,24 @@ def test_refine_fd_fp32_and_autograd(kbm, oracle_mod):
         fd[:, j] = (lp.astype(np.float64) - lm) / (pp[:, j].astype(np.float64) - pm[:, j])
     rel = np.linalg.norm(fd - g, axis=1) / np.maximum(np.linalg.norm(g, axis=1), 1e-3)
     assert np.median(rel) < 1e-2
+
+
+@pytest.mark.parametrize("quantity,ql,qh", [(1, 0.25, 0.75), (0, 0.1, 0.9), (1, 0.16, 0.84)])
+def test_sigmag_filter_variants(kbm, oracle_mod, quantity, ql, qh):
+    """Flux quantity, other quantile pairs with C of Eq. 3, and the ΣLH'
+    post-filter flag: keep masks bit-identical to the oracle."""
+    rng = np.random.default_rng(90 + quantity)
+    n, T = 20000, 26
+    ps = rng.normal(0, 3, (n, T)).astype(np.float32)
+    ps[:, 5] += rng.choice([0, 50], n).astype(np.float32)
+    ph = rng.uniform(0.1, 4, (n, T)).astype(np.float32)
+    ph[::17, 3] = 0.0
+    c = kbm.sigmag_coeff(ql, qh)
+    keep, lh, ok = kbm.sigmag_filter_ex(_cuda(ps), _cuda(ph), quantity=quantity, q_lo=ql,
+                                        q_hi=qh, coeff=c, lh_min=2.0)
+    rk, rl = oracle_mod.sigmag(ps, ph, q_lo=ql, q_hi=qh, coeff=c, quantity=quantity)
+    assert np.array_equal(keep.cpu().numpy().view(np.uint64), rk)
+    assert np.all(P.lh_close(lh.cpu().numpy(), rl))
+    g_ok = ok.cpu().numpy()
+    near = np.abs(rl - 2.0) <= 1e-4 * np.maximum(np.abs(rl), 1.0)
+    assert np.all((g_ok == (rl >= 2.0)) | near)
