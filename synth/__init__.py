@@ -301,6 +301,44 @@ def make_batched_stack(spec: dict, n_vel=(64, 64), n_sources: int = 20) -> Stack
                       name=f"c3-{spec['seed']}")
 
 
+def add_static_artifacts(st: Stack, n: int, seed: int, psf_sigma: float,
+                         snr_range=(20.0, 60.0), run=(5, 9),
+                         gap_days: float = 0.5) -> List[dict]:
+    """Add ``n`` static artifacts to ``st.sci`` in place: each a PSF-shaped
+    blob at a fixed sub-pixel position, present in a run of consecutive
+    epochs of one night (``run`` epochs, at least 5: the intranight repeats
+    of a differencing residual), with per-epoch matched-filter SNR drawn
+    from ``snr_range``.  Nights are groups of epochs separated by more than
+    ``gap_days``.  Returns the artifacts' descriptions."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T, H, W = st.sci.shape
+    r = psf_size(psf_sigma) // 2
+    s2 = float(np.sum(gaussian_psf(psf_sigma).astype(np.float64) ** 2))
+    order = np.argsort(st.times)
+    nights, cur = [], [int(order[0])]
+    for a, b in zip(order[:-1], order[1:]):
+        if st.times[b] - st.times[a] > gap_days:
+            nights.append(cur)
+            cur = []
+        cur.append(int(b))
+    nights.append(cur)
+    out = []
+    for _ in range(n):
+        night = nights[int(rng.integers(0, len(nights)))]
+        m = int(min(len(night), rng.integers(run[0], run[1] + 1)))
+        first = int(rng.integers(0, len(night) - m + 1))
+        epochs = night[first:first + m]
+        x = float(rng.uniform(r + 1, W - r - 2))
+        y = float(rng.uniform(r + 1, H - r - 2))
+        snr = float(rng.uniform(*snr_range))
+        flux = snr * math.sqrt(SKY / s2)
+        x0, y0, g = _stamp(psf_sigma, r, x, y, flux)
+        for e in epochs:
+            st.sci[e, y0:y0 + g.shape[0], x0:x0 + g.shape[1]] += g.astype(np.float32)
+        out.append(dict(x=x, y=y, epochs=epochs, snr=snr, flux=flux))
+    return out
+
+
 def tiny_stack(seed: int, W: int = 12, H: int = 10, T: int = 4, k: int = 3,
                n_vel: int = 6, mask_rate: float = 0.15, masked_fill=None,
                max_speed: float = 6.0) -> Stack:
