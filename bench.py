@@ -301,6 +301,9 @@ def main():
         "schedule": plan.schedule,
         "top_slot_filled_frac": valid_frac,
         "refine": {"candidates": n_cand,
+                   "ms_per_adam_step": st_ms["refine"] / REFINE_STEPS,
+                   "candidate_epochs_per_s": n_cand * T * REFINE_STEPS /
+                   (st_ms["refine"] / 1e3) if n_cand else None,
                    "median_lh_grid": float(lh0.median().item()) if n_cand else None,
                    "median_lh_refined": float(lh_ref.median().item()) if n_cand else None,
                    "frac_improved": float((lh_ref >= lh0).double().mean().item())
