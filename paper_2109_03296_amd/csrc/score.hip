@@ -77,13 +77,13 @@ __global__ __launch_bounds__(256) void score_kernel(ScoreArgs a) {
                 hi |= k ? (1u << (i - 32)) : 0u;
         }
     }
-    const float L = P / sqrtf(F);
+    const float L = srch::lh_value(P, F);
     a.nobs[j] = (int16_t)nv;
     if (nv >= a.min_obs && nv > 0 && isfinite(L)) {
         a.lh[j] = L;
         a.flux[j] = P / F;
         a.keep[j] = (uint64_t)lo | ((uint64_t)hi << 32);
-        if (a.lh_raw) a.lh_raw[j] = Pr / sqrtf(Fr);
+        if (a.lh_raw) a.lh_raw[j] = srch::lh_value(Pr, Fr);
     } else {
         a.lh[j] = -INFINITY;
         a.flux[j] = 0.0f;

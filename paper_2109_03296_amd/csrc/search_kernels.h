@@ -168,6 +168,14 @@ __device__ __forceinline__ float2 pack_sample(float psi, float phi, bool &bad) {
     return ok ? make_float2(psi / sb, sb) : make_float2(__builtin_nanf(""), 0.0f);
 }
 
+// L = Psi / sqrt(Phi) as the search ranks and stores it: one hardware
+// reciprocal square root (1 ulp) and a product, a few ulp from the
+// correctly rounded quotient.  Every kernel that forms a search likelihood
+// uses this one function, so equal inputs give equal bits everywhere.
+__device__ __forceinline__ float lh_value(float P, float F) {
+    return P * __builtin_amdgcn_rsqf(F);
+}
+
 struct Score {
     float L, flux;
     uint64_t keep;
@@ -215,7 +223,7 @@ __device__ __forceinline__ Score score(const A &a,
         }
     }
     r.keep = (uint64_t)lo | ((uint64_t)hi << 32);
-    r.L = P / sqrtf(F);
+    r.L = lh_value(P, F);
     r.flux = P / F;
     return r;
 }
@@ -244,7 +252,7 @@ __device__ __forceinline__ float score_fixed(const A &a,
             F = fmaf(s[i], s[i], F);
         }
     }
-    return P / sqrtf(F);
+    return lh_value(P, F);
 }
 
 // Whole-wave in-bounds load: the per-epoch offset is wave-uniform.
@@ -525,7 +533,7 @@ __device__ __forceinline__ void finalize_pixel(const A &a,
                     F = fmaf(s[i], s[i], F);
                 }
             }
-            a.lh_raw[o] = P / sqrtf(F);
+            a.lh_raw[o] = lh_value(P, F);
         }
     }
 }
