@@ -255,6 +255,52 @@ __device__ __forceinline__ float score_fixed(const A &a,
     return lh_value(P, F);
 }
 
+// Nearest ranks floor(q (n-1) + 1/2) of the default quantiles 1/4, 1/2, 3/4
+// in integer form (exact: (n+1)/4, n/2, (3n-1)/4 rounded down).
+constexpr int rank_q1(int n) { return n < 1 ? 0 : (n + 1) / 4; }
+constexpr int rank_q2(int n) { return n < 1 ? 0 : n / 2; }
+constexpr int rank_q3(int n) { return n < 1 ? 0 : (3 * n - 1) / 4; }
+
+// Sorted value at the rank of n = nv usable epochs, for nv in [T-3, T]:
+// four compile-time positions and a pick by nv.
+template <int T, int R0, int R1, int R2, int R3>
+__device__ __forceinline__ float pick_near(const float (&srt)[T], int nv) {
+    const float v0 = srt[R0], v1 = srt[R1], v2 = srt[R2], v3 = srt[R3];
+    return nv == T ? v0 : nv == T - 1 ? v1 : nv == T - 2 ? v2 : v3;
+}
+
+// Filtered likelihood with the default quantiles when every lane has at
+// least T-3 usable epochs (unusable ones are NaN and sort last): the sorting
+// network only has to produce the positions the ranks of T..T-3 usable
+// epochs reach (7 of 26 for T = 26), so it is pruned almost as far as the
+// all-usable network.  Same sorted values, ranks and arithmetic as score().
+template <int T, class A>
+__device__ __forceinline__ float score_near(const A &a, const float (&nu)[T],
+                                            const float (&s)[T], int nv) {
+#pragma clang fp contract(off)
+    float srt[T];
+#pragma unroll
+    for (int i = 0; i < T; ++i) srt[i] = (nu[i] == nu[i]) ? nu[i] : INFINITY;
+    sort_network<T>(srt);
+    const float x_lo =
+        pick_near<T, rank_q1(T), rank_q1(T - 1), rank_q1(T - 2), rank_q1(T - 3)>(srt, nv);
+    const float x_md =
+        pick_near<T, rank_q2(T), rank_q2(T - 1), rank_q2(T - 2), rank_q2(T - 3)>(srt, nv);
+    const float x_hi =
+        pick_near<T, rank_q3(T), rank_q3(T - 1), rank_q3(T - 2), rank_q3(T - 3)>(srt, nv);
+    SigmaGCut c;
+    c.x_md = x_md;
+    c.thr = a.n_sigma * (a.coeff * (x_hi - x_lo));
+    float P = 0.0f, F = 0.0f;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        const bool k = c.keeps(nu[i]);
+        P = fmaf(k ? nu[i] : 0.0f, s[i], P);
+        F = fmaf(k ? s[i] : 0.0f, s[i], F);
+    }
+    return lh_value(P, F);
+}
+
 // Whole-wave in-bounds load: the per-epoch offset is wave-uniform.
 template <int TM, bool CLEAN, bool EXACT, int AM, class A>
 __device__ __forceinline__ int load_fast(const A &a,
@@ -392,6 +438,9 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
                                                      cst(a.lin) + (size_t)v * T, nu, s);
             if (EXACT && CLEAN && a.defq)
                 sc.L = score_fixed<TM>(a, nu, s);
+            else if (EXACT && !CLEAN && TM >= 4 && a.defq && a.sigmag &&
+                     __all(nv >= TM - 3))
+                sc.L = score_near<TM>(a, nu, s, nv);
             else
                 sc = score<TM, !CLEAN, EXACT>(a, nu, s, nv);
         } else {
