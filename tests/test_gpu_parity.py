@@ -76,6 +76,56 @@ def test_planes_protocol_A(kbm, oracle_mod, case):
     assert np.all(np.abs(gphi - rphi) <= 1e-5 * rphi + 1e-30)
 
 
+def _rotated_psf(k, sx=1.8, sy=0.9, theta=0.6):
+    """Elliptical Gaussian rotated off the axes: not an outer product."""
+    r = k // 2
+    y, x = np.mgrid[-r:r + 1, -r:r + 1].astype(np.float64)
+    u = np.cos(theta) * x + np.sin(theta) * y
+    v = -np.sin(theta) * x + np.cos(theta) * y
+    g = np.exp(-0.5 * (u * u / (sx * sx) + v * v / (sy * sy)))
+    return (g / g.sum()).astype(np.float32)
+
+
+@pytest.mark.parametrize("psf_case", ["rotated9", "gauss25", "delta1", "gauss_rowzero"])
+def test_planes_psf_shapes(kbm, oracle_mod, psf_case):
+    """Rank-1 PSFs take the two-pass kernel, others the direct one; both
+    meet the same bound against the oracle (including the widest PSF and
+    a ragged 3-tile x 3-tile image)."""
+    _say(f"planes psf shapes: {psf_case}")
+    st = synth.tiny_stack(11, W=150, H=37, T=3, k=5, mask_rate=0.1)
+    if psf_case == "rotated9":
+        st.psf = _rotated_psf(9)
+    elif psf_case == "gauss25":
+        st.psf = synth.gaussian_psf(3.0, 25)
+    elif psf_case == "delta1":
+        st.psf = np.ones((1, 1), np.float32)
+    else:
+        g = synth.gaussian_psf(1.2, 7).astype(np.float64)
+        g[0, :] = 0.0      # still an outer product, with a zero factor entry
+        st.psf = (g / g.sum()).astype(np.float32)
+    psi, phi = kbm.make_planes(_cuda(st.sci), _cuda(st.var), _cuda(st.mask), st.psf)
+    rpsi, rphi = oracle_mod.planes(st.sci, st.var, st.mask, st.psf)
+    terms = P.plane_terms_abs(oracle_mod, st.sci, st.var, st.mask, st.psf)
+    gpsi, gphi = psi.cpu().numpy(), phi.cpu().numpy()
+    assert np.all(np.abs(gpsi - rpsi) <= 1e-5 * terms + 1e-30)
+    assert np.all(np.abs(gphi - rphi) <= 1e-5 * rphi + 1e-30)
+
+
+def test_planes_separable_matches_direct(kbm):
+    """The same Gaussian through both kernels: a perturbation of one tap by
+    1e-4 of the peak (well above the rank-1 test's 1e-6) sends it to the
+    direct kernel; the results agree to the size of that perturbation."""
+    st = synth.tiny_stack(12, W=130, H=50, T=4, k=9, mask_rate=0.1)
+    g = st.psf.copy()
+    h = g.copy()
+    h[0, 0] += np.float32(1e-4) * g.max()
+    a = kbm.make_planes(_cuda(st.sci), _cuda(st.var), _cuda(st.mask), g)
+    b = kbm.make_planes(_cuda(st.sci), _cuda(st.var), _cuda(st.mask), h)
+    scale = float(torch.max(torch.abs(a[0])))
+    assert float(torch.max(torch.abs(a[0] - b[0]))) < 1e-3 * scale
+    assert not torch.equal(a[0], b[0])
+
+
 def test_planes_masked_fill_bitwise(kbm):
     a = synth.tiny_stack(4, W=70, H=33, T=5, k=7, mask_rate=0.3)
     b = synth.tiny_stack(4, W=70, H=33, T=5, k=7, mask_rate=0.3, masked_fill=1e30)
