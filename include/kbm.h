@@ -76,6 +76,9 @@ typedef struct {
  * i.e. correlation with the PSF (matched filter), r = (psf_k-1)/2, taps
  * outside the image add nothing.  Masked pixels are removed by selection,
  * so any value under the mask (NaN, 1e30) never reaches the planes.
+ * A PSF that equals an outer product c_b r_a to within 1e-6 of its largest
+ * tap (a sampled Gaussian) is applied as a row pass then a column pass; the
+ * result differs from the direct double sum by binary32 rounding only.
  *
  *   sci, var : device float [T][H][W]
  *   mask     : device uint8 [T][H][W], nonzero = masked; may be NULL
