@@ -78,8 +78,15 @@ kbm_status check_sigmag_params(double q_lo, double q_hi, double coeff,
 // ---------------------------------------------------------------------
 
 // Batcher's odd-even merge sort on N registers (any N), fully unrolled.
-// All indices are compile-time constants, so the array stays in VGPRs and
-// every comparator is one v_min_f32 + one v_max_f32.
+// All indices are compile-time constants, so the array stays in VGPRs.
+// Comparators use IEEE 754-2019 minimum/maximum (v_minimum3_f32 /
+// v_maximum3_f32): callers never pass NaN (unusable entries arrive as
+// +inf), and unlike fminf/fmaxf these need no quieting of operands the
+// compiler cannot prove quiet (values loaded as raw bits), which would cost
+// one extra instruction per element.  The only difference from fminf/fmaxf
+// on NaN-free input is that -0 orders before +0; the two compare equal, so
+// every rank value, difference and threshold built from the sorted array
+// is unchanged.
 template <int N>
 __device__ __forceinline__ void sort_network(float (&a)[N]) {
 #pragma unroll
@@ -92,8 +99,8 @@ __device__ __forceinline__ void sort_network(float (&a)[N]) {
                 for (int i = 0; i < k; ++i) {
                     if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
                         const float x = a[i + j], y = a[i + j + k];
-                        a[i + j] = fminf(x, y);
-                        a[i + j + k] = fmaxf(x, y);
+                        a[i + j] = __builtin_elementwise_minimum(x, y);
+                        a[i + j + k] = __builtin_elementwise_maximum(x, y);
                     }
                 }
             }
