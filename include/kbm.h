@@ -39,7 +39,7 @@ extern "C" {
 
 #define KBM_MAX_EPOCHS 64   /* keep masks are 64-bit */
 #define KBM_MAX_K 16        /* results per pixel */
-#define KBM_MAX_PSF 25      /* odd PSF width limit */
+#define KBM_MAX_PSF 31      /* odd PSF width limit */
 
 typedef enum {
     KBM_OK = 0,
@@ -176,7 +176,7 @@ typedef struct {
                               probe (0 when not tuned) */
 } kbm_schedule;
 
-#define KBM_TUNE_DEFAULT 0 /* built-in schedule: vel_block 1024, 4 x 16
+#define KBM_TUNE_DEFAULT 0 /* built-in schedule: vel_block 2048, 2 x 32
                               super-tiles, 4 waves, all that fit */
 #define KBM_TUNE_AUTO 1    /* time candidate schedules on a probe, keep the
                               fastest (cached per process by batch shape) */

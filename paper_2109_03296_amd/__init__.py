@@ -33,7 +33,7 @@ __all__ = [
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkbm.so")
-MAX_EPOCHS, MAX_K, MAX_PSF = 64, 16, 25
+MAX_EPOCHS, MAX_K, MAX_PSF = 64, 16, 31
 
 _lock = threading.Lock()
 _lib = None

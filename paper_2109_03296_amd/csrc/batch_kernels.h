@@ -37,6 +37,12 @@ struct StackInfo {
     uint32_t pad;
 };
 
+// Register budget of the batched kernel: at least this many waves per SIMD
+// (3: up to 168 VGPRs per lane).
+#ifndef KBM_BATCH_MIN_WAVES
+#define KBM_BATCH_MIN_WAVES 3
+#endif
+
 // Merge buffers of the four-wave variant (the only code that touches them,
 // so single-wave kernels allocate no LDS for them).
 __shared__ float g_mL[3 * BKM * WAVE];
@@ -85,7 +91,7 @@ static __device__ __noinline__ void batch_tile(const SearchArgs *descs, int s, i
 
 template <int NWT>
 __global__ __launch_bounds__(WAVE * NWT)
-__attribute__((amdgpu_waves_per_eu(3, 8)))
+__attribute__((amdgpu_waves_per_eu(KBM_BATCH_MIN_WAVES, 8)))
 void batch_kernel(const SearchArgs *__restrict__ descs,
                   const StackInfo *__restrict__ info,
                   const uint32_t *__restrict__ pre, const int2 *__restrict__ seg,

@@ -29,18 +29,24 @@ constexpr int MAX_R = (KBM_MAX_PSF - 1) / 2;
 constexpr int LDS_W = TILE_X + 2 * MAX_R;
 constexpr int LDS_H = TILE_Y + 2 * MAX_R;
 
+// PSF rows b0 .. b0+nb-1 of one launch, in kernel arguments.  The direct
+// kernel takes at most PSF_ARG_MAX taps per launch (kernel arguments stay
+// well under 4 KB); a wider PSF is applied in two launches over row ranges,
+// the second adding its partial sums to the first's.
+constexpr int PSF_ARG_MAX = 640;
 struct PsfArg {
-    float p[KBM_MAX_PSF * KBM_MAX_PSF];
+    float p[PSF_ARG_MAX];
 };
 
 __global__ __launch_bounds__(THREADS) void planes_kernel(
     const float *__restrict__ sci, const float *__restrict__ var,
     const uint8_t *__restrict__ mask, float *__restrict__ psi,
-    float *__restrict__ phi, int W, int H, int k, PsfArg psf) {
+    float *__restrict__ phi, int W, int H, int k, int b0, int nb, int accumulate,
+    PsfArg psf) {
     __shared__ float s_u[LDS_H * LDS_W];
     __shared__ float s_w[LDS_H * LDS_W];
-    __shared__ float s_p[KBM_MAX_PSF * KBM_MAX_PSF];
-    __shared__ float s_p2[KBM_MAX_PSF * KBM_MAX_PSF];
+    __shared__ float s_p[PSF_ARG_MAX];
+    __shared__ float s_p2[PSF_ARG_MAX];
 
     const int r = k / 2;
     const int tid = threadIdx.x;
@@ -49,7 +55,7 @@ __global__ __launch_bounds__(THREADS) void planes_kernel(
     const size_t plane = (size_t)blockIdx.z * ((size_t)W * H);
     const int lw = TILE_X + 2 * r, lh = TILE_Y + 2 * r;
 
-    for (int j = tid; j < k * k; j += THREADS) {
+    for (int j = tid; j < nb * k; j += THREADS) {
         const float p = psf.p[j];
         s_p[j] = p;
         s_p2[j] = p * p;
@@ -81,9 +87,9 @@ __global__ __launch_bounds__(THREADS) void planes_kernel(
         const int y = y0 + ly;
         if (y >= H) break;
         float a_psi = 0.0f, a_phi = 0.0f;
-        for (int b = 0; b < k; ++b) {
-            const float *ru = s_u + (ly + b) * LDS_W + tx;
-            const float *rw = s_w + (ly + b) * LDS_W + tx;
+        for (int b = 0; b < nb; ++b) {
+            const float *ru = s_u + (ly + b0 + b) * LDS_W + tx;
+            const float *rw = s_w + (ly + b0 + b) * LDS_W + tx;
             const float *pp = s_p + b * k;
             const float *pp2 = s_p2 + b * k;
             for (int a = 0; a < k; ++a) {
@@ -92,6 +98,10 @@ __global__ __launch_bounds__(THREADS) void planes_kernel(
             }
         }
         const size_t o = plane + (size_t)y * W + x;
+        if (accumulate) {
+            a_psi += psi[o];
+            a_phi += phi[o];
+        }
         psi[o] = a_psi;
         phi[o] = a_phi;
     }
@@ -240,16 +250,20 @@ extern "C" kbm_status kbm_make_planes(const kbm_stack *s, const float *sci,
             KBM_SEP_CASE(1) KBM_SEP_CASE(3) KBM_SEP_CASE(5) KBM_SEP_CASE(7)
             KBM_SEP_CASE(9) KBM_SEP_CASE(11) KBM_SEP_CASE(13) KBM_SEP_CASE(15)
             KBM_SEP_CASE(17) KBM_SEP_CASE(19) KBM_SEP_CASE(21) KBM_SEP_CASE(23)
-            KBM_SEP_CASE(25)
+            KBM_SEP_CASE(25) KBM_SEP_CASE(27) KBM_SEP_CASE(29) KBM_SEP_CASE(31)
 #undef KBM_SEP_CASE
         }
         KBM_LAUNCHED("planes_sep_kernel");
         return KBM_OK;
     }
-    PsfArg pa{};
-    for (int j = 0; j < psf_k * psf_k; ++j) pa.p[j] = psf[j];
-    hipLaunchKernelGGL(planes_kernel, grid, dim3(THREADS), 0, stream, sci, var,
-                       mask, psi, phi, W, H, (int)psf_k, pa);
-    KBM_LAUNCHED("planes_kernel");
+    const int rows = PSF_ARG_MAX / psf_k;  // >= 20 for psf_k <= 31
+    for (int b0 = 0; b0 < psf_k; b0 += rows) {
+        const int nb = std::min(rows, psf_k - b0);
+        PsfArg pa{};
+        for (int j = 0; j < nb * psf_k; ++j) pa.p[j] = psf[b0 * psf_k + j];
+        hipLaunchKernelGGL(planes_kernel, grid, dim3(THREADS), 0, stream, sci, var,
+                           mask, psi, phi, W, H, (int)psf_k, b0, nb, b0 > 0 ? 1 : 0, pa);
+        KBM_LAUNCHED("planes_kernel");
+    }
     return KBM_OK;
 }

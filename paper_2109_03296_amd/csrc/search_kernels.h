@@ -448,21 +448,26 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
                                               cst(a.lin) + (size_t)v * T, nu, s);
             sc = score<TM, true, EXACT>(a, nu, s, nv);
         }
-        if (active && nv >= a.min_obs && isfinite(sc.L) &&
-            ranks_before(sc.L, v, kL[KM - 1], kI[KM - 1])) {
-            kL[KM - 1] = sc.L;
-            kI[KM - 1] = v;
+        // Velocities reach a lane in increasing index order (within the
+        // sweep, across chunks, and in the state read back), so v exceeds
+        // every index in the list: under the tie rule an equal L keeps the
+        // older entry, and ranks_before(L, v, x, i) reduces to L > x.  The
+        // insertion is branch-free (some lane of the wave inserts at almost
+        // every velocity): c_j = (L > kL[j]) is false then true down the
+        // descending list, so slot j takes kL[j] before the insertion point,
+        // L at it and kL[j-1] after it.  A lane that does not insert uses
+        // L = -inf, for which every c_j is false.
+        const float xL = (active && nv >= a.min_obs && isfinite(sc.L)) ? sc.L : -INFINITY;
 #pragma unroll
-            for (int j = KM - 1; j > 0; --j) {
-                if (ranks_before(kL[j], kI[j], kL[j - 1], kI[j - 1])) {
-                    const float tl = kL[j];
-                    kL[j] = kL[j - 1];
-                    kL[j - 1] = tl;
-                    const int ti = kI[j];
-                    kI[j] = kI[j - 1];
-                    kI[j - 1] = ti;
-                }
-            }
+        for (int j = KM - 1; j > 0; --j) {
+            const bool cj = xL > kL[j], cp = xL > kL[j - 1];
+            kL[j] = cp ? kL[j - 1] : (cj ? xL : kL[j]);
+            kI[j] = cp ? kI[j - 1] : (cj ? v : kI[j]);
+        }
+        {
+            const bool c0 = xL > kL[0];
+            kL[0] = c0 ? xL : kL[0];
+            kI[0] = c0 ? v : kI[0];
         }
     }
     if (NWT > 1) {
@@ -507,25 +512,6 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         if (slot >= 0) {
             a.stL[(size_t)slot * npix + pix] = kL[j];
             a.stI[(size_t)slot * npix + pix] = kI[j];
-        }
-    }
-}
-
-// Insert (L, v) into a lane's sorted top-K registers.
-template <int KM>
-__device__ __forceinline__ void topk_insert(float (&kL)[KM], int (&kI)[KM],
-                                            float L, int v) {
-    kL[KM - 1] = L;
-    kI[KM - 1] = v;
-#pragma unroll
-    for (int j = KM - 1; j > 0; --j) {
-        if (ranks_before(kL[j], kI[j], kL[j - 1], kI[j - 1])) {
-            const float tl = kL[j];
-            kL[j] = kL[j - 1];
-            kL[j - 1] = tl;
-            const int ti = kI[j];
-            kI[j] = kI[j - 1];
-            kI[j - 1] = ti;
         }
     }
 }

@@ -60,9 +60,9 @@ def test_make_planes_validation(L):
     assert L.kbm_make_planes(None, FAKE, FAKE, None, pp, 3, FAKE, FAKE, None) == 1
     assert L.kbm_make_planes(C.byref(st), FAKE, FAKE, None, pp, 4, FAKE, FAKE, None) == 1
     assert b"odd" in L.kbm_last_error()
-    big = np.ones((27, 27), np.float32)
+    big = np.ones((33, 33), np.float32)
     assert L.kbm_make_planes(C.byref(st), FAKE, FAKE, None,
-                             big.ctypes.data_as(C.c_void_p), 27, FAKE, FAKE, None) == 2
+                             big.ctypes.data_as(C.c_void_p), 33, FAKE, FAKE, None) == 2
     assert L.kbm_make_planes(C.byref(st), None, FAKE, None, pp, 3, FAKE, FAKE, None) == 1
     st65, t65 = _stack(T=65)
     assert L.kbm_make_planes(C.byref(st65), FAKE, FAKE, None, pp, 3, FAKE, FAKE, None) == 1

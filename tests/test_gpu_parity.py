@@ -86,17 +86,22 @@ def _rotated_psf(k, sx=1.8, sy=0.9, theta=0.6):
     return (g / g.sum()).astype(np.float32)
 
 
-@pytest.mark.parametrize("psf_case", ["rotated9", "gauss25", "delta1", "gauss_rowzero"])
+@pytest.mark.parametrize("psf_case", ["rotated9", "gauss25", "delta1", "gauss_rowzero",
+                                      "gauss31", "rotated31"])
 def test_planes_psf_shapes(kbm, oracle_mod, psf_case):
-    """Rank-1 PSFs take the two-pass kernel, others the direct one; both
-    meet the same bound against the oracle (including the widest PSF and
-    a ragged 3-tile x 3-tile image)."""
+    """Rank-1 PSFs take the two-pass kernel, others the direct one (a
+    direct PSF wider than 25 in two launches over row ranges); all meet the
+    same bound against the oracle, on a ragged 3-tile x 3-tile image."""
     _say(f"planes psf shapes: {psf_case}")
     st = synth.tiny_stack(11, W=150, H=37, T=3, k=5, mask_rate=0.1)
     if psf_case == "rotated9":
         st.psf = _rotated_psf(9)
     elif psf_case == "gauss25":
         st.psf = synth.gaussian_psf(3.0, 25)
+    elif psf_case == "gauss31":
+        st.psf = synth.gaussian_psf(4.0, 31)
+    elif psf_case == "rotated31":   # direct kernel over two row ranges
+        st.psf = _rotated_psf(31, sx=5.0, sy=2.5)
     elif psf_case == "delta1":
         st.psf = np.ones((1, 1), np.float32)
     else:
