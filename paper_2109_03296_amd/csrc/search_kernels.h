@@ -302,11 +302,11 @@ __device__ __forceinline__ float score_near(const A &a, const float (&nu)[T],
 }
 
 // Whole-wave in-bounds load: the per-epoch offset is wave-uniform.
-template <int TM, bool CLEAN, bool EXACT, int AM, class A>
+template <int TM, bool CLEAN, bool EXACT, int AM, class A, class LV>
 __device__ __forceinline__ int load_fast(const A &a,
                                          const PlaneRsrc &rs,
                                          uint32_t lane, uint32_t wave_e,
-                                         const KBM_CONST uint32_t *lv, float (&nu)[TM],
+                                         const LV &lv, float (&nu)[TM],
                                          float (&s)[TM]) {
     const int T = EXACT ? TM : a.T;
     int nv = 0;
@@ -330,11 +330,11 @@ __device__ __forceinline__ int load_fast(const A &a,
 }
 
 // General load with per-lane bounds checks.
-template <int TM, bool EXACT, int AM, class A>
+template <int TM, bool EXACT, int AM, class A, class LV>
 __device__ __forceinline__ int load_slow(const A &a,
                                          const PlaneRsrc &rs, int x,
                                          int y, const KBM_CONST int *ov,
-                                         const KBM_CONST uint32_t *lv, float (&nu)[TM],
+                                         const LV &lv, float (&nu)[TM],
                                          float (&s)[TM]) {
     const int T = EXACT ? TM : a.T;
     const uint32_t pix = (uint32_t)(y * a.W + x);
@@ -416,12 +416,26 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         }
     }
 
+    // Lanes past the region end never insert: their candidate is clamped to
+    // -inf by a per-lane value.  The empty asm hides where the value comes
+    // from, so the compiler keeps one VGPR instead of turning the clamp back
+    // into a select on a lane mask held in scalar registers for the whole
+    // sweep (which it spills).
+    float gate = active ? INFINITY : -INFINITY;
+    asm volatile("" : "+v"(gate));
     const uint32_t wave_e = (uint32_t)(y * a.W + xw);
     for (int v = v_begin + w; v < v_end; v += NWT) {
+        // The velocity's box and offset row are read up front, as one
+        // batch of scalar loads with one wait, and the box test combines
+        // its four comparisons without short-circuit branches (each branch
+        // would wait for its own scalar load).
         const int4 bx = ld_box(a.vbox, v);
-        const bool fast = xw + bx.x >= 0 &&
-                          xw + (WAVE - 1) + bx.y < a.W && y + bx.z >= 0 &&
-                          y + bx.w < a.H;
+        const KBM_CONST uint32_t *lvp = cst(a.lin) + (size_t)v * T;
+        uint32_t lv[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) lv[i] = i < T ? lvp[i] : 0u;
+        const bool fast = (xw + bx.x >= 0) & (xw + (WAVE - 1) + bx.y < a.W) &
+                          (y + bx.z >= 0) & (y + bx.w < a.H);
         if (!fast) {
             // Sound skip: if fewer than min_obs epochs can hold any lane of
             // this wave in the image (per axis), no lane reaches min_obs.
@@ -434,8 +448,7 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         int nv;
         Score sc;
         if (fast) {
-            nv = load_fast<TM, CLEAN, EXACT, AM>(a, rs, lane, wave_e,
-                                                     cst(a.lin) + (size_t)v * T, nu, s);
+            nv = load_fast<TM, CLEAN, EXACT, AM>(a, rs, lane, wave_e, lv, nu, s);
             if (EXACT && CLEAN && a.defq)
                 sc.L = score_fixed<TM>(a, nu, s);
             else if (EXACT && !CLEAN && TM >= 4 && a.defq && a.sigmag &&
@@ -444,8 +457,8 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
             else
                 sc = score<TM, !CLEAN, EXACT>(a, nu, s, nv);
         } else {
-            nv = load_slow<TM, EXACT, AM>(a, rs, x, y, cst(a.off16) + (size_t)v * T,
-                                              cst(a.lin) + (size_t)v * T, nu, s);
+            nv = load_slow<TM, EXACT, AM>(a, rs, x, y, cst(a.off16) + (size_t)v * T, lv,
+                                          nu, s);
             sc = score<TM, true, EXACT>(a, nu, s, nv);
         }
         // Velocities reach a lane in increasing index order (within the
@@ -457,7 +470,8 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         // descending list, so slot j takes kL[j] before the insertion point,
         // L at it and kL[j-1] after it.  A lane that does not insert uses
         // L = -inf, for which every c_j is false.
-        const float xL = (active && nv >= a.min_obs && isfinite(sc.L)) ? sc.L : -INFINITY;
+        const float xL = __builtin_elementwise_minimum(
+            (nv >= a.min_obs && isfinite(sc.L)) ? sc.L : -INFINITY, gate);
 #pragma unroll
         for (int j = KM - 1; j > 0; --j) {
             const bool cj = xL > kL[j], cp = xL > kL[j - 1];
