@@ -397,6 +397,13 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     const int T = EXACT ? TM : a.T;
     const PlaneRsrc rs = plane_rsrc(a);
 
+    // Wave 0 continues the pixel's running list.  The other waves start
+    // from K copies of that list's K-th best L with index -1: only a
+    // trajectory that beats it can reach the merged top K (an equal L loses
+    // the tie to the older entry), so they insert as rarely as wave 0 does,
+    // and the merge skips the index -1 fillers.
+    float thr = -INFINITY;
+    if (!first && active && w != 0) thr = a.stL[(size_t)(a.K - 1) * npix + pix];
     float kL[KM];
     int kI[KM];
 #pragma unroll
@@ -408,7 +415,7 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
             kL[j] = INFINITY;
             kI[j] = -2;
         } else if (first || !active || w != 0) {
-            kL[j] = -INFINITY;
+            kL[j] = thr;
             kI[j] = -1;
         } else {
             kL[j] = a.stL[(size_t)slot * npix + pix];
@@ -421,7 +428,9 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     // from, so the compiler keeps one VGPR instead of turning the clamp back
     // into a select on a lane mask held in scalar registers for the whole
     // sweep (which it spills).
-    float gate = active ? INFINITY : -INFINITY;
+    // In a stack without unusable samples every fast-path trajectory has
+    // n_obs = T, so the min_obs test is folded into the gate as well.
+    float gate = (active && (!CLEAN || T >= a.min_obs)) ? INFINITY : -INFINITY;
     asm volatile("" : "+v"(gate));
     const uint32_t wave_e = (uint32_t)(y * a.W + xw);
     for (int v = v_begin + w; v < v_end; v += NWT) {
@@ -469,16 +478,18 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         // every velocity): c_j = (L > kL[j]) is false then true down the
         // descending list, so slot j takes kL[j] before the insertion point,
         // L at it and kL[j-1] after it.  A lane that does not insert uses
-        // L = -inf, for which every c_j is false.
+        // L = -inf, for which every c_j is false.  Once the list holds good
+        // entries most velocities insert in no lane and skip the block.
+        const bool obs_ok = (CLEAN && fast) || nv >= a.min_obs;
         const float xL = __builtin_elementwise_minimum(
-            (nv >= a.min_obs && isfinite(sc.L)) ? sc.L : -INFINITY, gate);
+            (obs_ok && isfinite(sc.L)) ? sc.L : -INFINITY, gate);
+        if (__any(xL > kL[KM - 1])) {
 #pragma unroll
-        for (int j = KM - 1; j > 0; --j) {
-            const bool cj = xL > kL[j], cp = xL > kL[j - 1];
-            kL[j] = cp ? kL[j - 1] : (cj ? xL : kL[j]);
-            kI[j] = cp ? kI[j - 1] : (cj ? v : kI[j]);
-        }
-        {
+            for (int j = KM - 1; j > 0; --j) {
+                const bool cj = xL > kL[j], cp = xL > kL[j - 1];
+                kL[j] = cp ? kL[j - 1] : (cj ? xL : kL[j]);
+                kI[j] = cp ? kI[j - 1] : (cj ? v : kI[j]);
+            }
             const bool c0 = xL > kL[0];
             kL[0] = c0 ? xL : kL[0];
             kI[0] = c0 ? v : kI[0];
