@@ -176,8 +176,9 @@ typedef struct {
                               probe (0 when not tuned) */
 } kbm_schedule;
 
-#define KBM_TUNE_DEFAULT 0 /* built-in schedule: vel_block 2048, 2 x 32
-                              super-tiles, 4 waves, all that fit */
+#define KBM_TUNE_DEFAULT 0 /* built-in schedule: vel_block 2048 if some
+                              stack has >= 16384 velocities else 1024,
+                              2 x 32 super-tiles, 4 waves, all that fit */
 #define KBM_TUNE_AUTO 1    /* time candidate schedules on a probe, keep the
                               fastest (cached per process by batch shape) */
 #define KBM_TUNE_GIVEN 2   /* use *schedule as given */

@@ -60,12 +60,13 @@ struct Sched {
 
 bool pow2_in(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
 
-// Built-in schedule: 2048 velocities per item, 4 wavefronts per workgroup
-// sharing a tile (each sweeps every fourth velocity), 128 px x 32 row
-// super-tiles, as many workgroups as fit.  Measured on the DECam-CCD stack
-// (2048 x 4096, T = 26, 128^2 velocities) and on 62 stacks of 64^2
-// velocities, it beats 1024 x (4 x 16) by 3% and 1.6%.
-Sched default_sched() { return Sched{2048, 2, 32, 4, 0}; }
+// Built-in schedule: 4 wavefronts per workgroup sharing a tile (each sweeps
+// every fourth velocity), 128 px x 32 row super-tiles, as many workgroups as
+// fit, and 2048 velocities per item when some stack has at least 16384
+// velocities, else 1024.  Measured: the DECam-CCD stack (2048 x 4096,
+// T = 26, 128^2 velocities) runs best at 2048 (1024: +2.8%, 3072: +0.7%),
+// 62 stacks of 64^2 velocities at 1024 (2048: +3.9%).
+Sched default_sched(int vmax) { return Sched{vmax >= 16384 ? 2048 : 1024, 2, 32, 4, 0}; }
 
 }  // namespace batch
 }  // namespace kbm
@@ -311,7 +312,7 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
     KBM_HIP(hipEventCreate(&e0));
     KBM_HIP(hipEventCreate(&e1));
     kbm_status st = KBM_OK;
-    Sched cur = default_sched();
+    Sched cur = default_sched(vmax);
     float cur_ms = 0.0f, ms = 0.0f;
     auto run = [&](const Sched &c, float *t) -> kbm_status {
         return probe(b, c, div, stream, e0, e1, t);
@@ -328,8 +329,9 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
             }
             return s2;
         };
-        const int vbs[] = {512, 1024, 4096};
+        const int vbs[] = {512, 1024, 2048, 4096};
         for (int v : vbs) {
+            if (v == cur.vb) continue;
             if (v / 2 >= vmax) continue;  // same single block as a smaller one
             Sched c = cur;
             c.vb = v;
@@ -410,7 +412,9 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
     KBM_REQUIRE(tune == KBM_TUNE_DEFAULT || tune == KBM_TUNE_AUTO || tune == KBM_TUNE_GIVEN,
                 KBM_ERR_INVALID_ARG, "kbm_batch_create: tune = %d is not a KBM_TUNE_ mode",
                 tune);
-    Sched given = default_sched();
+    int vmax = 0;
+    for (int j = 0; j < num_stacks; ++j) vmax = std::max(vmax, (int)p[j].num_vel);
+    Sched given = default_sched(vmax);
     if (tune == KBM_TUNE_GIVEN) {
         KBM_REQUIRE(schedule != nullptr, KBM_ERR_INVALID_ARG,
                     "kbm_batch_create: KBM_TUNE_GIVEN needs a schedule");

@@ -301,6 +301,28 @@ __device__ __forceinline__ float score_near(const A &a, const float (&nu)[T],
     return lh_value(P, F);
 }
 
+// One velocity's per-epoch offsets.  Up to 32 epochs they are loaded into
+// scalar registers when constructed; above that the row stays in memory and
+// each entry is loaded where it is used (holding 33..64 offsets would spill
+// scalar registers).
+template <int TM, bool HOLD = (TM <= 32)>
+struct LinRow;
+template <int TM>
+struct LinRow<TM, true> {
+    uint32_t v[TM];
+    __device__ __forceinline__ LinRow(const KBM_CONST uint32_t *p, int T) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) v[i] = i < T ? p[i] : 0u;
+    }
+    __device__ __forceinline__ uint32_t operator[](int i) const { return v[i]; }
+};
+template <int TM>
+struct LinRow<TM, false> {
+    const KBM_CONST uint32_t *p;
+    __device__ __forceinline__ LinRow(const KBM_CONST uint32_t *q, int) : p(q) {}
+    __device__ __forceinline__ uint32_t operator[](int i) const { return p[i]; }
+};
+
 // Whole-wave in-bounds load: the per-epoch offset is wave-uniform.
 template <int TM, bool CLEAN, bool EXACT, int AM, class A, class LV>
 __device__ __forceinline__ int load_fast(const A &a,
@@ -434,15 +456,12 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     asm volatile("" : "+v"(gate));
     const uint32_t wave_e = (uint32_t)(y * a.W + xw);
     for (int v = v_begin + w; v < v_end; v += NWT) {
-        // The velocity's box and offset row are read up front, as one
-        // batch of scalar loads with one wait, and the box test combines
-        // its four comparisons without short-circuit branches (each branch
-        // would wait for its own scalar load).
+        // The velocity's box (and for T <= 32 its offset row) is read up
+        // front, as one batch of scalar loads with one wait, and the box
+        // test combines its four comparisons without short-circuit branches
+        // (each branch would wait for its own scalar load).
         const int4 bx = ld_box(a.vbox, v);
-        const KBM_CONST uint32_t *lvp = cst(a.lin) + (size_t)v * T;
-        uint32_t lv[TM];
-#pragma unroll
-        for (int i = 0; i < TM; ++i) lv[i] = i < T ? lvp[i] : 0u;
+        const LinRow<TM> lv(cst(a.lin) + (size_t)v * T, T);
         const bool fast = (xw + bx.x >= 0) & (xw + (WAVE - 1) + bx.y < a.W) &
                           (y + bx.z >= 0) & (y + bx.w < a.H);
         if (!fast) {
