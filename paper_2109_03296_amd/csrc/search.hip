@@ -80,8 +80,8 @@ StackLayout layout(const kbm_stack &s, const kbm_search_params &p,
     l.tab_off = align_up(l.pk_off + l.pk_bytes, 256);
     l.off_rel = 0;
     l.lin_rel = align_up(l.off_rel + sizeof(int) * V * T, 16);
-    l.box_rel = align_up(l.lin_rel + sizeof(uint32_t) * V * T, 16);
-    l.mbox_rel = align_up(l.box_rel + sizeof(int4) * V, 16);
+    l.box_rel = align_up(l.lin_rel + sizeof(uint32_t) * V * T, 32);
+    l.mbox_rel = align_up(l.box_rel + 2 * sizeof(int4) * V, 16);
     l.rank_rel = align_up(l.mbox_rel + sizeof(int4) * V, 16);
     l.tab_bytes = l.rank_rel + sizeof(int) * 3 * 65;
     l.flags_off = align_up(l.tab_off + l.tab_bytes, 256);
@@ -151,7 +151,9 @@ kbm_status check_search(const kbm_stack *stacks, const kbm_search_params *p,
 //    (sides <= 32767);
 //  * lin: i H W + dy W + dx modulo 2^32, the element offset of epoch i's
 //    sample relative to the start pixel;
-//  * vbox: each velocity's offset bounding box;
+//  * vbox: each velocity's offset bounding box, then two masks of the
+//    epochs below 32 whose offsets equal those of velocity v-1 and of v-4
+//    (a wave that sweeps every first or fourth velocity keeps those samples);
 //  * mbox: the min_obs-th smallest and largest dx and dy of each velocity
 //    (a wave can only reach min_obs usable epochs if, per axis, that many
 //    epochs keep some lane inside the image);
@@ -165,7 +167,7 @@ void make_tables(const kbm_stack &s, const kbm_search_params &p,
     int *off = reinterpret_cast<int *>(buf.data() + l.off_rel);
     uint32_t *lin = reinterpret_cast<uint32_t *>(buf.data() + l.lin_rel);
     const int64_t HW = (int64_t)s.width * s.height;
-    int4 *box = reinterpret_cast<int4 *>(buf.data() + l.box_rel);
+    int4 *box = reinterpret_cast<int4 *>(buf.data() + l.box_rel);  // [V][2]
     int4 *mbox = reinterpret_cast<int4 *>(buf.data() + l.mbox_rel);
     std::vector<int> sx(T), sy(T);
     const int m = std::min(p.min_obs, T);
@@ -191,13 +193,24 @@ void make_tables(const kbm_stack &s, const kbm_search_params &p,
             sx[i] = cx;
             sy[i] = cy;
         }
-        box[v] = b;
+        box[2 * v] = b;
         std::sort(sx.begin(), sx.end());
         std::sort(sy.begin(), sy.end());
         if (p.min_obs > T)  // no trajectory can qualify: always skip
             mbox[v] = make_int4(INT32_MAX / 2, INT32_MIN / 2, INT32_MAX / 2, INT32_MIN / 2);
         else
             mbox[v] = make_int4(sx[m - 1], sx[T - m], sy[m - 1], sy[T - m]);
+    }
+    for (int v = 0; v < V; ++v) {
+        uint32_t same[2] = {0u, 0u};
+        const int stride[2] = {1, 4};
+        for (int k = 0; k < 2; ++k) {
+            if (v < stride[k]) continue;
+            const uint32_t *a = lin + (size_t)v * T, *b = lin + (size_t)(v - stride[k]) * T;
+            for (int i = 0; i < std::min(T, 32); ++i)
+                if (a[i] == b[i]) same[k] |= 1u << i;
+        }
+        box[2 * v + 1] = make_int4((int)same[0], (int)same[1], 0, 0);
     }
     const RankTable rt = make_rank_table(p.q_lo, p.q_hi);
     for (int n = 0; n <= KBM_MAX_EPOCHS; ++n) {

@@ -99,7 +99,8 @@ struct SearchArgs {
     int am;                   // addressing mode of this stack (0, 1, 2)
     const int *off16;         // [V][T] (dx & 0xffff) | (dy << 16)
     const uint32_t *lin;      // [V][T] i H W + dy W + dx (mod 2^32)
-    const int4 *vbox;         // [V] (dxmin, dxmax, dymin, dymax)
+    const int4 *vbox;         // [V][2] (dxmin, dxmax, dymin, dymax), (same1, same4, 0, 0):
+                              // masks of epochs < 32 offset as at velocity v-1, v-4
     const int4 *mbox;         // [V] min_obs-th smallest/largest dx and dy
     const int *ranks;         // [3][65] quantile ranks by usable count
     const int *flags;         // [0] != 0: some pixel-epoch is unusable
@@ -324,31 +325,44 @@ struct LinRow<TM, false> {
 };
 
 // Whole-wave in-bounds load: the per-epoch offset is wave-uniform.
+// Leading epochs whose samples a wave keeps from one velocity to the next
+// (the carried registers); past these every epoch is loaded.
+constexpr int KBM_CARRY = 10;
+
+// Epochs below KBM_CARRY whose bit is set in `keep` (wave-uniform) are not
+// loaded: nu and s still hold this wave's samples of the previous velocity
+// it swept, whose offsets for those epochs are the same.
 template <int TM, bool CLEAN, bool EXACT, int AM, class A, class LV>
 __device__ __forceinline__ int load_fast(const A &a,
                                          const PlaneRsrc &rs,
                                          uint32_t lane, uint32_t wave_e,
-                                         const LV &lv, float (&nu)[TM],
+                                         const LV &lv, int keep, float (&nu)[TM],
                                          float (&s)[TM]) {
     const int T = EXACT ? TM : a.T;
-    int nv = 0;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         if (i < T) {
-            const uint32_t e = wave_e + lv[i];
-            const float2 q = AM > 0 ? ld_plane(second_group<AM, EXACT ? TM / 2 : -1>(a, i)
-                                                   ? rs.r1 : rs.r0,
-                                               lane * 8u, e * 8u)
-                                    : a.pk[(size_t)e + lane];
-            nu[i] = q.x;
-            s[i] = q.y;
-            if (!CLEAN) nv += (q.x == q.x) ? 1 : 0;
+            if (i >= KBM_CARRY || !((keep >> i) & 1)) {
+                const uint32_t e = wave_e + lv[i];
+                const float2 q =
+                    AM > 0 ? ld_plane(second_group<AM, EXACT ? TM / 2 : -1>(a, i) ? rs.r1
+                                                                                  : rs.r0,
+                                      lane * 8u, e * 8u)
+                           : a.pk[(size_t)e + lane];
+                nu[i] = q.x;
+                s[i] = q.y;
+            }
         } else {
             nu[i] = INFINITY;
             s[i] = 0.0f;
         }
     }
-    return CLEAN ? T : nv;
+    if (CLEAN) return T;
+    int nv = 0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+        if (i < T) nv += (nu[i] == nu[i]) ? 1 : 0;
+    return nv;
 }
 
 // General load with per-lane bounds checks.
@@ -455,12 +469,20 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     float gate = (active && (!CLEAN || T >= a.min_obs)) ? INFINITY : -INFINITY;
     asm volatile("" : "+v"(gate));
     const uint32_t wave_e = (uint32_t)(y * a.W + xw);
+    // The first KBM_CARRY entries of nu and s carry over between velocities:
+    // `have` says they hold the fast-path samples of velocity v - NWT (the
+    // previous one this wave swept).  Not above 32 epochs, where the carried
+    // registers would cost occupancy.
+    constexpr int NC = TM > 32 ? 0 : TM < KBM_CARRY ? TM : KBM_CARRY;
+    float cnu[NC > 0 ? NC : 1], cs[NC > 0 ? NC : 1];
+    int have = 0;
     for (int v = v_begin + w; v < v_end; v += NWT) {
         // The velocity's box (and for T <= 32 its offset row) is read up
         // front, as one batch of scalar loads with one wait, and the box
         // test combines its four comparisons without short-circuit branches
         // (each branch would wait for its own scalar load).
-        const int4 bx = ld_box(a.vbox, v);
+        const int4 bx = ld_box(a.vbox, 2 * v);
+        const int same = cst((const int *)a.vbox)[8 * (size_t)v + (NWT == 4 ? 5 : 4)];
         const LinRow<TM> lv(cst(a.lin) + (size_t)v * T, T);
         const bool fast = (xw + bx.x >= 0) & (xw + (WAVE - 1) + bx.y < a.W) &
                           (y + bx.z >= 0) & (y + bx.w < a.H);
@@ -469,14 +491,29 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
             // this wave in the image (per axis), no lane reaches min_obs.
             const int4 mb = ld_box(a.mbox, v);
             if (xw + mb.x > a.W - 1 || xw + (WAVE - 1) + mb.y < 0 ||
-                y + mb.z > a.H - 1 || y + mb.w < 0)
+                y + mb.z > a.H - 1 || y + mb.w < 0) {
+                have = 0;
                 continue;
+            }
         }
         float nu[TM], s[TM];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            nu[i] = cnu[i];
+            s[i] = cs[i];
+        }
         int nv;
         Score sc;
         if (fast) {
-            nv = load_fast<TM, CLEAN, EXACT, AM>(a, rs, lane, wave_e, lv, nu, s);
+            nv = load_fast<TM, CLEAN, EXACT, AM>(
+                a, rs, lane, wave_e, lv, (NC > 0 && have && (NWT == 1 || NWT == 4)) ? same : 0,
+                nu, s);
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                cnu[i] = nu[i];
+                cs[i] = s[i];
+            }
+            have = 1;
             if (EXACT && CLEAN && a.defq)
                 sc.L = score_fixed<TM>(a, nu, s);
             else if (EXACT && !CLEAN && TM >= 4 && a.defq && a.sigmag &&
@@ -487,6 +524,7 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         } else {
             nv = load_slow<TM, EXACT, AM>(a, rs, x, y, cst(a.off16) + (size_t)v * T, lv,
                                           nu, s);
+            have = 0;
             sc = score<TM, true, EXACT>(a, nu, s, nv);
         }
         // Velocities reach a lane in increasing index order (within the

@@ -96,7 +96,8 @@ def test_search_validation_and_workspace_size(L):
     def up(x, a=256):
         return math.ceil(x / a) * a
     T, H, W, V, K = 5, 8, 9, 3, 4
-    tab = up(up(up(up(V * T * 4, 16) + V * T * 4, 16) + V * 16, 16) + V * 16, 16) + 3 * 65 * 4
+    # off16, lin, per-velocity box + repeat counts (32 B), mbox (16 B), ranks
+    tab = up(up(up(up(V * T * 4, 16) + V * T * 4, 32) + V * 32, 16) + V * 16, 16) + 3 * 65 * 4
     pk = up(T * H * W * 8)
     flags = up(pk + tab)
     stl = up(flags + 256)
