@@ -36,7 +36,8 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # Kernel sources of the persistent search kernel; a traffic figure taken
 # with hardware counters is reported only while these are unchanged.
-KERNEL_SOURCES = ["batch_kernels.h", "batch_nw1.hip", "batch_nw4.hip",
+KERNEL_SOURCES = ["batch_kernels.h", "batch_nw1.hip", "batch_nw4.hip", "batch_nw1c.hip",
+                  "batch_nw4c.hip",
                   "search_kernels.h", "kbm_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_kernel_c2_counters.md")
 N_CANDIDATES = 100_000

@@ -172,13 +172,16 @@ typedef struct {
     int32_t tile_rows;     /* super-tile height in rows: 1,2,4,...,64 */
     int32_t waves;         /* wavefronts per workgroup sharing a tile: 1 or 4 */
     int32_t blocks_per_cu; /* persistent workgroups per CU; 0 = all that fit */
+    int32_t sweep;         /* velocity order of a workgroup's waves: 0 = wave w
+                              takes every waves-th velocity from w, 1 = wave w
+                              takes the w-th contiguous share of the block */
     float probe_ms;        /* out: time of this schedule on the autotuner's
                               probe (0 when not tuned) */
 } kbm_schedule;
 
-#define KBM_TUNE_DEFAULT 0 /* built-in schedule: vel_block 2048 if some
-                              stack has >= 16384 velocities else 1024,
-                              2 x 32 super-tiles, 4 waves, all that fit */
+#define KBM_TUNE_DEFAULT 0 /* built-in schedule: vel_block 1024, 2 x 32
+                              super-tiles, 4 waves, all that fit, sweep 1 if
+                              some stack has >= 16384 velocities else 0 */
 #define KBM_TUNE_AUTO 1    /* time candidate schedules on a probe, keep the
                               fastest (cached per process by batch shape) */
 #define KBM_TUNE_GIVEN 2   /* use *schedule as given */

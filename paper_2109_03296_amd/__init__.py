@@ -114,7 +114,8 @@ class Schedule(C.Structure):
     """Schedule of the batched persistent search (see ``kbm_schedule``)."""
     _fields_ = [("vel_block", C.c_int32), ("tile_cols", C.c_int32),
                 ("tile_rows", C.c_int32), ("waves", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("probe_ms", C.c_float)]
+                ("blocks_per_cu", C.c_int32), ("sweep", C.c_int32),
+                ("probe_ms", C.c_float)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -19,8 +19,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkbm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.cpp", "planes.hip", "search.hip", "search_exact_a.hip",
-           "search_exact_b.hip", "sigmag.hip", "refine.hip", "extract.hip", "batch.hip", "batch_nw1.hip",
-           "batch_nw4.hip", "score.hip", "stamps.hip"]
+           "search_exact_b.hip", "sigmag.hip", "refine.hip", "extract.hip", "batch.hip",
+           "batch_nw1.hip", "batch_nw1c.hip", "batch_nw4.hip", "batch_nw4c.hip", "score.hip",
+           "stamps.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

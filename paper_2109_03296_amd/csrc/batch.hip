@@ -55,18 +55,19 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(const PrepDesc *__restr
 }
 
 struct Sched {
-    int vb, st_x, st_y, nw, bpc;
+    int vb, st_x, st_y, nw, bpc, sw;
 };
 
 bool pow2_in(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
 
-// Built-in schedule: 4 wavefronts per workgroup sharing a tile (each sweeps
-// every fourth velocity), 128 px x 32 row super-tiles, as many workgroups as
-// fit, and 2048 velocities per item when some stack has at least 16384
-// velocities, else 1024.  Measured: the DECam-CCD stack (2048 x 4096,
-// T = 26, 128^2 velocities) runs best at 2048 (1024: +2.8%, 3072: +0.7%),
-// 62 stacks of 64^2 velocities at 1024 (2048: +3.9%).
-Sched default_sched(int vmax) { return Sched{vmax >= 16384 ? 2048 : 1024, 2, 32, 4, 0}; }
+// Built-in schedule: 1024 velocities per item, 4 wavefronts per workgroup
+// sharing a tile, 128 px x 32 row super-tiles, as many workgroups as fit;
+// the waves take contiguous shares of the item's velocities when some stack
+// has at least 16384 velocities, else every fourth velocity.  Measured: the
+// DECam-CCD stack (2048 x 4096, T = 26, 128^2 velocities) takes 1183 ms this
+// way (interleaved: 1236 ms at its best block, 2048); 62 stacks of 64^2
+// velocities take 10.54 s (contiguous: 10.76 s at its best block, 512).
+Sched default_sched(int vmax) { return Sched{1024, 2, 32, 4, 0, vmax >= 16384 ? 1 : 0}; }
 
 }  // namespace batch
 }  // namespace kbm
@@ -156,6 +157,8 @@ kbm_status check_sched(const Sched &s) {
                 "kbm_batch: waves = %d must be 1 or 4", s.nw);
     KBM_REQUIRE(s.bpc >= 0 && s.bpc <= 64, KBM_ERR_INVALID_ARG,
                 "kbm_batch: blocks_per_cu = %d not in [0, 64]", s.bpc);
+    KBM_REQUIRE(s.sw == 0 || s.sw == 1, KBM_ERR_INVALID_ARG,
+                "kbm_batch: sweep = %d must be 0 or 1", s.sw);
     return KBM_OK;
 }
 
@@ -221,12 +224,12 @@ kbm_status write_schedule(kbm_batch *b, const Sched &sc, int div, hipStream_t st
     return KBM_OK;
 }
 
-kbm_status blocks_per_cu(int nw, int *out) {
+kbm_status blocks_per_cu(int nw, int sw, int *out) {
     int nb = 0;
     if (nw == 1)
-        KBM_HIP(occupancy_nw1(&nb));
+        KBM_HIP(sw ? occupancy_nw1c(&nb) : occupancy_nw1(&nb));
     else
-        KBM_HIP(occupancy_nw4(&nb));
+        KBM_HIP(sw ? occupancy_nw4c(&nb) : occupancy_nw4(&nb));
     *out = std::max(nb, 1);
     return KBM_OK;
 }
@@ -234,7 +237,7 @@ kbm_status blocks_per_cu(int nw, int *out) {
 // Schedule with blocks_per_cu = 0 replaced by the occupancy limit.
 kbm_status resolve(Sched *sc) {
     if (sc->bpc != 0) return KBM_OK;
-    return blocks_per_cu(sc->nw, &sc->bpc);
+    return blocks_per_cu(sc->nw, sc->sw, &sc->bpc);
 }
 
 // Enqueue clear -> pack -> persistent search for schedule `sc` (already
@@ -253,8 +256,10 @@ kbm_status enqueue_run(kbm_batch *b, const Sched &sc, hipStream_t stream,
     const BatchLaunch l{b->descs, b->info, b->pre, b->seg, b->ctrl,
                         b->prog, b->nseg, sc.vb, sc.st_x, sc.st_y};
     if (ev0) KBM_HIP(hipEventRecord(ev0, stream));
-    const hipError_t e = sc.nw == 1 ? launch_batch_nw1(l, grid, stream)
-                                    : launch_batch_nw4(l, grid, stream);
+    const hipError_t e = sc.nw == 1 ? (sc.sw ? launch_batch_nw1c(l, grid, stream)
+                                             : launch_batch_nw1(l, grid, stream))
+                                    : (sc.sw ? launch_batch_nw4c(l, grid, stream)
+                                             : launch_batch_nw4(l, grid, stream));
     if (e != hipSuccess) {
         set_error("launch of batch_kernel failed: %s", hipGetErrorString(e));
         return KBM_ERR_DEVICE;
@@ -290,8 +295,8 @@ std::string shape_key(const kbm_batch *b, const kbm_search_params *p) {
     return k;
 }
 
-// Coordinate descent over velocity block, super-tile shape, waves per
-// workgroup and workgroups per CU, each candidate timed once on a probe of
+// Coordinate descent over sweep order, velocity block, super-tile shape,
+// waves per workgroup and workgroups per CU, each candidate timed once on a probe of
 // 1/16 of every stack's tiles (after one warm-up run).
 kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream,
                     Sched *best, float *best_ms) {
@@ -329,6 +334,11 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
             }
             return s2;
         };
+        {
+            Sched c = cur;
+            c.sw = 1 - cur.sw;
+            if ((st = consider(c)) != KBM_OK) break;
+        }
         const int vbs[] = {512, 1024, 2048, 4096};
         for (int v : vbs) {
             if (v == cur.vb) continue;
@@ -352,7 +362,7 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
             if ((st = consider(c)) != KBM_OK) break;
         }
         int full = 1;
-        if ((st = blocks_per_cu(cur.nw, &full)) != KBM_OK) break;
+        if ((st = blocks_per_cu(cur.nw, cur.sw, &full)) != KBM_OK) break;
         for (int num : {3, 2}) {
             Sched c = cur;
             c.bpc = std::max(1, full * num / 4);
@@ -419,7 +429,7 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
         KBM_REQUIRE(schedule != nullptr, KBM_ERR_INVALID_ARG,
                     "kbm_batch_create: KBM_TUNE_GIVEN needs a schedule");
         given = Sched{schedule->vel_block, schedule->tile_cols, schedule->tile_rows,
-                      schedule->waves, schedule->blocks_per_cu};
+                      schedule->waves, schedule->blocks_per_cu, schedule->sweep};
         st = check_sched(given);
         if (st != KBM_OK) return st;
     }
@@ -579,6 +589,7 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
         schedule->tile_rows = sc.st_y;
         schedule->waves = sc.nw;
         schedule->blocks_per_cu = sc.bpc;
+        schedule->sweep = sc.sw;
         schedule->probe_ms = b->probe_ms;
     }
     *batch_out = b;

@@ -60,22 +60,22 @@ __device__ __forceinline__ const KBM_CONST SearchArgs *uniform_desc(const Search
 // One work item for epoch count T.  Kept out of line so every epoch count
 // is register-allocated on its own; all arguments are wave-uniform and are
 // made scalar again on entry.
-template <int T, int NWT>
+template <int T, int NWT, bool CONTIG>
 static __device__ __noinline__ void batch_tile(const SearchArgs *descs, int s, int tx, int ty,
-                                        int v0, int v1, int first, int last) {
+                                        int v0, int v1, int flags) {
     const KBM_CONST SearchArgs &a = *uniform_desc(descs, s);
     tx = __builtin_amdgcn_readfirstlane(tx);
     ty = __builtin_amdgcn_readfirstlane(ty);
     v0 = __builtin_amdgcn_readfirstlane(v0);
     v1 = __builtin_amdgcn_readfirstlane(v1);
-    first = __builtin_amdgcn_readfirstlane(first);
-    last = __builtin_amdgcn_readfirstlane(last);
+    flags = __builtin_amdgcn_readfirstlane(flags);
+    const bool first = flags & 1, last = flags & 2;
     float *mL = NWT > 1 ? g_mL : nullptr;
     int *mI = NWT > 1 ? g_mI : nullptr;
     if (cst(a.flags)[0] == 0)
-        srch::run_chunk<T, BKM, true, true, 1, NWT>(a, tx, ty, v0, v1, first != 0, mL, mI);
+        srch::run_chunk<T, BKM, true, true, 1, NWT, CONTIG>(a, tx, ty, v0, v1, first, mL, mI);
     else
-        srch::run_chunk<T, BKM, false, true, 1, NWT>(a, tx, ty, v0, v1, first != 0, mL, mI);
+        srch::run_chunk<T, BKM, false, true, 1, NWT, CONTIG>(a, tx, ty, v0, v1, first, mL, mI);
     if (!last) return;
     const int w = NWT > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)) : 0;
     const int rx = tx * WAVE + (int)(threadIdx.x % WAVE);
@@ -86,10 +86,10 @@ static __device__ __noinline__ void batch_tile(const SearchArgs *descs, int s, i
 
 #define KBM_BATCH_CASE(n)                                                      \
     case n:                                                                    \
-        batch_tile<n, NWT>(descs, s, tx, ty, v0, v1, first, last);             \
+        batch_tile<n, NWT, CONTIG>(descs, s, tx, ty, v0, v1, flags);           \
         break;
 
-template <int NWT>
+template <int NWT, bool CONTIG>
 __global__ __launch_bounds__(WAVE * NWT)
 __attribute__((amdgpu_waves_per_eu(KBM_BATCH_MIN_WAVES, 8)))
 void batch_kernel(const SearchArgs *__restrict__ descs,
@@ -161,7 +161,7 @@ void batch_kernel(const SearchArgs *__restrict__ descs,
             __syncthreads();
         }
         const int v0 = vb * vbs, v1 = min(a.V, v0 + vbs);
-        const int first = vb == 0, last = v1 == a.V;
+        const int flags = (vb == 0 ? 1 : 0) | (v1 == a.V ? 2 : 0);
         switch (a.T) {
             KBM_BATCH_CASE(1) KBM_BATCH_CASE(2) KBM_BATCH_CASE(3) KBM_BATCH_CASE(4)
             KBM_BATCH_CASE(5) KBM_BATCH_CASE(6) KBM_BATCH_CASE(7) KBM_BATCH_CASE(8)
@@ -176,14 +176,14 @@ void batch_kernel(const SearchArgs *__restrict__ descs,
         // The item's waves must all have left run_chunk (wave 0 wrote the
         // lists) before the lists are published.
         __syncthreads();
-        if (!last && threadIdx.x == 0)
+        if (!(flags & 2) && threadIdx.x == 0)
             __hip_atomic_store(pc, (uint32_t)(vb + 1), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// Launch of batch_kernel<NWT> and its occupancy (workgroups per CU); one
-// definition per wavefront count.
+// Launch of batch_kernel<NWT, CONTIG> and its occupancy (workgroups per
+// CU); one translation unit per wavefront count and sweep order.
 struct BatchLaunch {
     const SearchArgs *descs;
     const StackInfo *info;
@@ -194,8 +194,12 @@ struct BatchLaunch {
 };
 hipError_t launch_batch_nw1(const BatchLaunch &l, unsigned grid, hipStream_t stream);
 hipError_t launch_batch_nw4(const BatchLaunch &l, unsigned grid, hipStream_t stream);
+hipError_t launch_batch_nw1c(const BatchLaunch &l, unsigned grid, hipStream_t stream);
+hipError_t launch_batch_nw4c(const BatchLaunch &l, unsigned grid, hipStream_t stream);
 hipError_t occupancy_nw1(int *blocks);
 hipError_t occupancy_nw4(int *blocks);
+hipError_t occupancy_nw1c(int *blocks);
+hipError_t occupancy_nw4c(int *blocks);
 
 }  // namespace batch
 }  // namespace kbm

@@ -1,18 +1,19 @@
-// Batched persistent search kernel, 4 wavefronts per workgroup.
+// Batched persistent search kernel, 4 wavefronts per workgroup, waves interleave an item's velocities.
 #include "batch_kernels.h"
 
 namespace kbm {
 namespace batch {
 
 hipError_t launch_batch_nw4(const BatchLaunch &l, unsigned grid, hipStream_t stream) {
-    hipLaunchKernelGGL(batch_kernel<4>, dim3(grid), dim3(WAVE * 4), 0, stream, l.descs,
-                       l.info, l.pre, l.seg, l.ctrl, l.prog, l.nseg, l.vbs, l.st_x, l.st_y);
+    hipLaunchKernelGGL((batch_kernel<4, false>), dim3(grid), dim3(WAVE * 4), 0, stream,
+                       l.descs, l.info, l.pre, l.seg, l.ctrl, l.prog, l.nseg, l.vbs, l.st_x,
+                       l.st_y);
     return hipGetLastError();
 }
 
 hipError_t occupancy_nw4(int *blocks) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks, reinterpret_cast<const void *>(&batch_kernel<4>), WAVE * 4, 0);
+        blocks, reinterpret_cast<const void *>(&batch_kernel<4, false>), WAVE * 4, 0);
 }
 
 }  // namespace batch

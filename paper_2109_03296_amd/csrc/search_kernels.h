@@ -414,7 +414,8 @@ __device__ __forceinline__ bool map_tile(const SearchArgs &a, int &tx, int &ty) 
 // first set the running lists start empty, else they are read from the
 // workspace; they are written back at the end.  mL/mI point to an LDS block
 // of (NW-1)*KM*WAVE entries each (unused when NW == 1).
-template <int TM, int KM, bool CLEAN, bool EXACT, int AM, int NWT = NW, class A>
+template <int TM, int KM, bool CLEAN, bool EXACT, int AM, int NWT = NW, bool CONTIG = false,
+          class A>
 __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
                                           int v_begin, int v_end, bool first,
                                           float *mL, int *mI) {
@@ -476,13 +477,22 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     constexpr int NC = TM > 32 ? 0 : TM < KBM_CARRY ? TM : KBM_CARRY;
     float cnu[NC > 0 ? NC : 1], cs[NC > 0 ? NC : 1];
     int have = 0;
-    for (int v = v_begin + w; v < v_end; v += NWT) {
+    // Wave w sweeps v_begin + w, v_begin + w + NWT, ... (interleaved: the
+    // waves read nearly the same rows at a time) or, with CONTIG, the w-th
+    // contiguous share of [v_begin, v_end) (consecutive velocities repeat
+    // more offsets, whose samples stay in registers).
+    const int span = CONTIG ? (v_end - v_begin + NWT - 1) / NWT : 0;
+    const int v_first = CONTIG ? v_begin + w * span : v_begin + w;
+    const int v_last = CONTIG ? min(v_end, v_first + span) : v_end;
+    constexpr int v_step = CONTIG ? 1 : NWT;
+    constexpr int same_at = (CONTIG || NWT == 1) ? 4 : 5;
+    for (int v = v_first; v < v_last; v += v_step) {
         // The velocity's box (and for T <= 32 its offset row) is read up
         // front, as one batch of scalar loads with one wait, and the box
         // test combines its four comparisons without short-circuit branches
         // (each branch would wait for its own scalar load).
         const int4 bx = ld_box(a.vbox, 2 * v);
-        const int same = cst((const int *)a.vbox)[8 * (size_t)v + (NWT == 4 ? 5 : 4)];
+        const int same = cst((const int *)a.vbox)[8 * (size_t)v + same_at];
         const LinRow<TM> lv(cst(a.lin) + (size_t)v * T, T);
         const bool fast = (xw + bx.x >= 0) & (xw + (WAVE - 1) + bx.y < a.W) &
                           (y + bx.z >= 0) & (y + bx.w < a.H);
@@ -506,7 +516,7 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         Score sc;
         if (fast) {
             nv = load_fast<TM, CLEAN, EXACT, AM>(
-                a, rs, lane, wave_e, lv, (NC > 0 && have && (NWT == 1 || NWT == 4)) ? same : 0,
+                a, rs, lane, wave_e, lv, (NC > 0 && have && (CONTIG || NWT == 1 || NWT == 4)) ? same : 0,
                 nu, s);
 #pragma unroll
             for (int i = 0; i < NC; ++i) {

@@ -149,8 +149,8 @@ def test_batch_validation(L):
     assert L.kbm_batch_create(C.byref(st), planes, planes, C.byref(p), res, 1, FAKE, big,
                               2, None, None, C.byref(h)) == 1
     for bad in (dict(vel_block=16), dict(tile_cols=3), dict(tile_rows=128),
-                dict(waves=2), dict(blocks_per_cu=-1)):
-        sc = kbm.Schedule(256, 4, 16, 1, 0, 0.0)
+                dict(waves=2), dict(blocks_per_cu=-1), dict(sweep=2)):
+        sc = kbm.Schedule(256, 4, 16, 1, 0, 0, 0.0)
         for f, v in bad.items():
             setattr(sc, f, v)
         assert L.kbm_batch_create(C.byref(st), planes, planes, C.byref(p), res, 1, FAKE,

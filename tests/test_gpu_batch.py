@@ -131,19 +131,24 @@ def test_batch_protocol_B(kbm, oracle_mod, batch):
 
 
 SCHEDULES = [
-    dict(vel_block=32, tile_cols=1, tile_rows=1, waves=1, blocks_per_cu=1),
-    dict(vel_block=1000, tile_cols=16, tile_rows=64, waves=4, blocks_per_cu=0),
-    dict(vel_block=64, tile_cols=2, tile_rows=32, waves=4, blocks_per_cu=2),
-    dict(vel_block=96, tile_cols=8, tile_rows=8, waves=1, blocks_per_cu=0),
+    dict(vel_block=32, tile_cols=1, tile_rows=1, waves=1, blocks_per_cu=1, sweep=0),
+    dict(vel_block=1000, tile_cols=16, tile_rows=64, waves=4, blocks_per_cu=0, sweep=0),
+    dict(vel_block=64, tile_cols=2, tile_rows=32, waves=4, blocks_per_cu=2, sweep=0),
+    dict(vel_block=96, tile_cols=8, tile_rows=8, waves=1, blocks_per_cu=0, sweep=0),
+    # contiguous shares, including a block that 4 waves do not divide evenly
+    dict(vel_block=100, tile_cols=2, tile_rows=32, waves=4, blocks_per_cu=0, sweep=1),
+    dict(vel_block=1000, tile_cols=4, tile_rows=16, waves=4, blocks_per_cu=3, sweep=1),
+    dict(vel_block=64, tile_cols=1, tile_rows=64, waves=1, blocks_per_cu=0, sweep=1),
 ]
 
 
-@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "vb%d_%dx%d_w%d_b%d" % (
-    s["vel_block"], s["tile_cols"], s["tile_rows"], s["waves"], s["blocks_per_cu"]))
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "vb%d_%dx%d_w%d_b%d_s%d" % (
+    s["vel_block"], s["tile_cols"], s["tile_rows"], s["waves"], s["blocks_per_cu"],
+    s["sweep"]))
 def test_batch_schedules_identical(kbm, batch, sched):
     _say(f"batch: schedule {sched}")
     res, used = _run(kbm, batch, sched)
-    for f in ("vel_block", "tile_cols", "tile_rows", "waves"):
+    for f in ("vel_block", "tile_cols", "tile_rows", "waves", "sweep"):
         assert used[f] == sched[f]
     for b, r in zip(batch, res):
         _equal(r, b["plain"])
