@@ -52,25 +52,28 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the persistent kernel from the committed
-    counter summary, or None when it is missing or was taken on other
-    kernel sources."""
+def measured_counters():
+    """Figures of the persistent kernel from the committed counter summary
+    (HBM bytes per launch, VALU busy fraction, L1 accesses per CU-cycle), or
+    {} when it is missing or was taken on other kernel sources."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
-        return None
+        return {}
     vals = {}
     for line in text.splitlines():
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for k in ("hbm_bytes_per_launch", "valu_busy", "l1_accesses_per_cu_cycle"):
+        try:
+            out[k] = float(vals[k])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def log(msg):
@@ -277,6 +280,7 @@ def main():
     lh0 = cand["lh"].double()
     n_cand = int(lh0.numel())
     lh_ref = last["lh"].double()
+    counters = measured_counters()
     rec = {
         "metric": "trajectory-epoch evals/s",
         "value": value,
@@ -312,7 +316,9 @@ def main():
         "roofline": {"bound": "alu", "kernel": "batch_kernel",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "ops_per_traj_epoch": ops, "traffic": measured_traffic(),
+                     "ops_per_traj_epoch": ops, "traffic": counters.get("hbm_bytes_per_launch"),
+                     "counters": {k: counters[k] for k in ("valu_busy", "l1_accesses_per_cu_cycle")
+                                  if k in counters} or None,
                      "kernel_source_hash": kernel_source_hash()},
     }
     if not args.no_check:
