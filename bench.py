@@ -83,14 +83,17 @@ def log(msg):
 def search_alg_ops(T, sigmag):
     """Algorithmic FP32 operations per trajectory-epoch of the search.
 
-    Plain path: the two running sums (Psi, Phi).  With sigma_G add, per
-    epoch: nu = psi/sqrt(phi) (a divide and a square root), its share of the
-    order statistics (ceil(log2 T) comparisons, the information-theoretic
-    comparison count per element of a sort), the distance to the median and
-    the threshold test (2), and the two kept sums (2)."""
+    Plain path: the two running sums (Psi, Phi).  With sigma_G, per epoch:
+    its share of the order statistics (ceil(log2 T) comparisons, the
+    information-theoretic comparison count per element of a sort), the
+    distance to the median and the threshold test (2), and the two kept
+    sums (2).  nu = psi/sqrt(phi) belongs to the pixel-epoch, not to the
+    trajectory (it is formed once per pixel-epoch, as is the plane), and the
+    unfiltered sums are needed only for the K results a pixel keeps, so
+    neither is counted per trajectory-epoch."""
     if not sigmag:
         return 2
-    return 2 + 2 + math.ceil(math.log2(max(T, 2))) + 2 + 2
+    return math.ceil(math.log2(max(T, 2))) + 2 + 2
 
 
 def cpu_baseline(st, params, log_fn):

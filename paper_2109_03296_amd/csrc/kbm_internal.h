@@ -10,8 +10,10 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <utility>
 
 #include "kbm.h"
+#include "sortnet.h"
 
 namespace kbm {
 
@@ -77,35 +79,50 @@ kbm_status check_sigmag_params(double q_lo, double q_hi, double coeff,
 // Device code: fixed-size sorting network and rank selection
 // ---------------------------------------------------------------------
 
-// Batcher's odd-even merge sort on N registers (any N), fully unrolled.
-// All indices are compile-time constants, so the array stays in VGPRs.
-// Comparators use IEEE 754-2019 minimum/maximum (v_minimum3_f32 /
-// v_maximum3_f32): callers never pass NaN (unusable entries arrive as
+// Sort N registers with the compile-time network of sortnet.h (3-sorter
+// runs joined by Batcher's odd-even merges; valid for every N, checked by
+// the 0-1 principle on the host).  Every wire index is a template constant,
+// so the array stays in VGPRs, and comparators whose outputs no caller
+// reads are dead code: with compile-time ranks only the ones that reach
+// them remain.  Compare-exchanges use IEEE 754-2019 minimum/maximum
+// (v_minimum3_f32 / v_maximum3_f32), 3-sorters v_minimum3_f32, v_med3_f32
+// and v_maximum3_f32.  Callers never pass NaN (unusable entries arrive as
 // +inf), and unlike fminf/fmaxf these need no quieting of operands the
 // compiler cannot prove quiet (values loaded as raw bits), which would cost
-// one extra instruction per element.  The only difference from fminf/fmaxf
-// on NaN-free input is that -0 orders before +0; the two compare equal, so
-// every rank value, difference and threshold built from the sorted array
-// is unchanged.
+// one extra instruction per element.  On NaN-free input the only freedom
+// left is the order of -0 and +0, which compare equal: every rank value,
+// difference and threshold built from the sorted array is the same.
+template <int N, int K>
+__device__ __forceinline__ void net_op(float (&a)[N]) {
+    constexpr net::Op o = net::Table<N>::net.op[K];
+    if constexpr (o.t == 0) {
+        const float x = a[o.a], y = a[o.b];
+        a[o.a] = __builtin_elementwise_minimum(x, y);
+        a[o.b] = __builtin_elementwise_maximum(x, y);
+    } else {
+        const float x = a[o.a], y = a[o.b], z = a[o.c];
+        a[o.a] = __builtin_elementwise_minimum(__builtin_elementwise_minimum(x, y), z);
+        a[o.b] = __builtin_amdgcn_fmed3f(x, y, z);
+        a[o.c] = __builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z);
+    }
+}
+
+template <int N, int... K>
+__device__ __forceinline__ void net_apply(float (&a)[N], std::integer_sequence<int, K...>) {
+    (net_op<N, K>(a), ...);
+}
+
+template <int N, int... R>
+__device__ __forceinline__ void net_to_ranks(float (&a)[N], std::integer_sequence<int, R...>) {
+    const float t[N] = {a[net::Table<N>::net.out[R]]...};
+#pragma unroll
+    for (int r = 0; r < N; ++r) a[r] = t[r];
+}
+
 template <int N>
 __device__ __forceinline__ void sort_network(float (&a)[N]) {
-#pragma unroll
-    for (int p = 1; p < N; p <<= 1) {
-#pragma unroll
-        for (int k = p; k >= 1; k >>= 1) {
-#pragma unroll
-            for (int j = k % p; j + k < N; j += 2 * k) {
-#pragma unroll
-                for (int i = 0; i < k; ++i) {
-                    if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
-                        const float x = a[i + j], y = a[i + j + k];
-                        a[i + j] = __builtin_elementwise_minimum(x, y);
-                        a[i + j + k] = __builtin_elementwise_maximum(x, y);
-                    }
-                }
-            }
-        }
-    }
+    net_apply<N>(a, std::make_integer_sequence<int, net::Table<N>::net.nops>{});
+    net_to_ranks<N>(a, std::make_integer_sequence<int, N>{});
 }
 
 constexpr int next_pow2(int n) {

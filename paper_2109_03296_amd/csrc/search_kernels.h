@@ -419,10 +419,8 @@ template <int TM, int KM, bool CLEAN, bool EXACT, int AM, int NWT = NW, bool CON
 __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
                                           int v_begin, int v_end, bool first,
                                           float *mL, int *mI) {
-    // NW waves share this tile's 64 start pixels and interleave the chunk's
-    // velocities (wave w takes v = v_begin + w, w + NW, ...), so at any time
-    // they read nearly the same plane rows: lines are shared through L1 and
-    // the per-XCD footprint of a velocity step shrinks NW-fold.
+    // NWT waves share this tile's 64 start pixels and split the chunk's
+    // velocities between them (interleaved or in contiguous shares, below).
     const unsigned lane = threadIdx.x % WAVE;
     const int w = NWT > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)) : 0;
     const int rx = tx * WAVE + (int)lane, ry = ty;
