@@ -6,15 +6,17 @@ replaces the dense grid by a coarse one: it searches the coarse grid
 (``search``), takes the global top-N result slots (``extract_top``), and
 moves each candidate to a sub-pixel start and a real-valued velocity by
 gradient ascent on the bilinear likelihood (``refine``: the adjoint kernel
-plus Adam).  Every step runs in the HIP kernels of libkbm; this module only
-sequences the calls and records per-stage times with HIP events.
+plus Adam).  ``known_objects`` evaluates a given list of trajectories
+(targeted mode: the search's filtered likelihood, then the median-stamp
+moment cut, Section 3.3).  Every step runs in the HIP kernels of libkbm; this
+module only sequences the calls and records per-stage times with HIP events.
 """
 from __future__ import annotations
 
 import torch
 
 from . import (SearchParams, extract_top, extract_workspace_size, refine,
-               score_trajectories, search, search_batched)
+               score_trajectories, search, search_batched, stamps)
 
 
 def coarse_to_fine(psi, phi, times, vels, params: SearchParams, n_candidates: int,
@@ -62,3 +64,29 @@ def coarse_to_fine(psi, phi, times, vels, params: SearchParams, n_candidates: in
                         extract=ev[1].elapsed_time(ev[2]),
                         refine=ev[2].elapsed_time(ev[3]),
                         score=ev[3].elapsed_time(ev[4])))
+
+
+def known_objects(sci, var, mask, psi, phi, times, params, search_params: SearchParams,
+                  lh_min: float = 10.0, radius: int = 10, stream=None):
+    """Targeted mode: evaluate the given linear trajectories ``params`` [n][4]
+    (x0, y0, vx, vy; float32, real-valued starts) with the search's filtered
+    likelihood (``score_trajectories``), then coadd median stamps over the
+    kept epochs and apply the central-moment cut (``stamps``).  A trajectory
+    is detected when its n_obs >= min_obs, L' >= lh_min and its stamp passes
+    the cut.  Returns a dict: lh, flux, keep, n_obs, moments, stamp_pass,
+    detected (bool [n]) and stage times in ms (score, stamps)."""
+    s = torch.cuda.current_stream() if stream is None else stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    prm = params.contiguous()
+    ev[0].record(s)
+    sc = score_trajectories(psi, phi, times, prm, search_params, want_lh_raw=False,
+                            stream=stream)
+    ev[1].record(s)
+    st = stamps(sci, var, mask, times, prm, keep=sc["keep"], radius=radius,
+                want_coadd=False, stream=stream)
+    ev[2].record(s)
+    ev[2].synchronize()
+    det = (sc["n_obs"] >= search_params.min_obs) & (sc["lh"] >= lh_min) & st["passed"]
+    return dict(lh=sc["lh"], flux=sc["flux"], keep=sc["keep"], n_obs=sc["n_obs"],
+                moments=st["moments"], stamp_pass=st["passed"], detected=det,
+                ms=dict(score=ev[0].elapsed_time(ev[1]), stamps=ev[1].elapsed_time(ev[2])))

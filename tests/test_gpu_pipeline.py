@@ -198,3 +198,48 @@ def test_score_trajectories_reproduces_search_slots(kbm, oracle_mod):
     g = kbm.score_trajectories(gpsi, gphi, st.times, prm, sp)
     for key in ("lh", "flux", "keep", "n_obs", "lh_raw"):
         assert torch.equal(g[key], res[key][ys, xs, ks]), key
+
+
+def _cuda(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_known_objects_targeted_mode(kbm, oracle_mod):
+    """Targeted mode on a DECam-CCD crop: the injected trajectories score
+    L' >= 10 (most of them), random decoys rarely do, every field equals the
+    separate score_trajectories / stamps calls, and L' matches the oracle."""
+    from paper_2109_03296_amd.pipeline import known_objects
+    st = synth.make_config(2, size=(1024, 1024), n_vel=(4, 4))
+    p = st.params
+    assert len(st.sources) >= 5
+    rng = np.random.default_rng(7)
+    true = np.array([[s["x0"], s["y0"], s["vx"], s["vy"]] for s in st.sources], np.float32)
+    decoy = np.stack([rng.uniform(0, 1024, 200), rng.uniform(0, 1024, 200),
+                      rng.uniform(-200, 200, 200), rng.uniform(-100, 100, 200)],
+                     1).astype(np.float32)
+    prm = np.concatenate([true, decoy])
+    sci, var = _cuda(st.sci), _cuda(st.var)
+    mask = _cuda(st.mask)
+    psi, phi = kbm.make_planes(sci, var, mask, st.psf, st.times)
+    sp = kbm.SearchParams(k=p["k"], min_obs=p["min_obs"], sigmag=True)
+    gp = torch.from_numpy(prm).cuda()
+    out = known_objects(sci, var, mask, psi, phi, st.times, gp, sp)
+    sc = kbm.score_trajectories(psi, phi, st.times, gp, sp)
+    sm = kbm.stamps(sci, var, mask, st.times, gp, keep=sc["keep"], radius=10,
+                    want_coadd=False)
+    for k in ("lh", "flux", "keep", "n_obs"):
+        assert torch.equal(out[k], sc[k]), k
+    # moments are NaN where a coadd sums to zero (no usable stamp pixel)
+    assert torch.equal(out["moments"].isnan(), sm["moments"].isnan())
+    assert torch.equal(out["moments"].nan_to_num(0.0), sm["moments"].nan_to_num(0.0))
+    assert torch.equal(out["stamp_pass"], sm["passed"])
+    lh = out["lh"].cpu().numpy()
+    det = ((out["n_obs"] >= p["min_obs"]) & (out["lh"] >= 10.0) & out["stamp_pass"])
+    assert torch.equal(out["detected"], det)
+    nt = len(true)
+    assert np.mean(lh[:nt] >= 10.0) >= 0.8, lh[:nt]
+    assert np.mean(lh[nt:] >= 10.0) < 0.05
+    ref = oracle_mod.score(psi.cpu().numpy(), phi.cpu().numpy(), st.times, prm, **p)
+    fin = np.isfinite(ref["lh"])
+    assert np.array_equal(np.isfinite(lh), fin)
+    assert np.all(np.abs(lh[fin] - ref["lh"][fin]) <= 1e-4 * np.maximum(np.abs(ref["lh"][fin]), 1))
