@@ -474,6 +474,11 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     // registers would cost occupancy.
     constexpr int NC = TM > 32 ? 0 : TM < KBM_CARRY ? TM : KBM_CARRY;
     float cnu[NC > 0 ? NC : 1], cs[NC > 0 ? NC : 1];
+#pragma unroll
+    for (int i = 0; i < (NC > 0 ? NC : 1); ++i) {
+        cnu[i] = 0.0f;
+        cs[i] = 0.0f;
+    }
     int have = 0;
     // Wave w sweeps v_begin + w, v_begin + w + NWT, ... (interleaved: the
     // waves read nearly the same rows at a time) or, with CONTIG, the w-th
