@@ -181,8 +181,8 @@ def main():
         print(json.dumps({"calib_copy_bytes": 4 * n}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build searches each stack on a "
-              "single MI355X (stacks are independent; see the sharding notes). "
+        print("bench.py measures one GPU only: each stack is searched on a single "
+              "MI355X (stacks are independent, so more GPUs take more stacks). "
               "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
