@@ -19,6 +19,7 @@ nominally, W * H * V * T per search, whatever the validity or pruning.
 """
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -38,17 +39,23 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # with hardware counters is reported only while these are unchanged.
 KERNEL_SOURCES = ["batch_kernels.h", "batch_nw1.hip", "batch_nw4.hip", "batch_nw1c.hip",
                   "batch_nw4c.hip",
-                  "search_kernels.h", "kbm_internal.h"]
+                  "search_kernels.h", "kbm_internal.h", "sortnet.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_kernel_c2_counters.md")
 N_CANDIDATES = 100_000
 REFINE_STEPS = 50
 
 
 def kernel_source_hash():
+    """Hash of the persistent kernel's sources with comments and blank
+    lines removed (a comment edit does not invalidate measured figures)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2109_03296_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2109_03296_amd", "csrc", f)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -462,16 +462,16 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     // -inf by a per-lane value.  The empty asm hides where the value comes
     // from, so the compiler keeps one VGPR instead of turning the clamp back
     // into a select on a lane mask held in scalar registers for the whole
-    // sweep (which it spills).
-    // In a stack without unusable samples every fast-path trajectory has
-    // n_obs = T, so the min_obs test is folded into the gate as well.
+    // sweep (which it spills).  In a stack without unusable samples every
+    // fast-path trajectory has n_obs = T, so the min_obs test is folded into
+    // the gate as well.
     float gate = (active && (!CLEAN || T >= a.min_obs)) ? INFINITY : -INFINITY;
     asm volatile("" : "+v"(gate));
     const uint32_t wave_e = (uint32_t)(y * a.W + xw);
     // The first KBM_CARRY entries of nu and s carry over between velocities:
-    // `have` says they hold the fast-path samples of velocity v - NWT (the
-    // previous one this wave swept).  Not above 32 epochs, where the carried
-    // registers would cost occupancy.
+    // `have` says they hold the fast-path samples of the previous velocity
+    // this wave swept (v - NWT interleaved, v - 1 contiguous).  Not above 32
+    // epochs, where the carried registers would cost occupancy.
     constexpr int NC = TM > 32 ? 0 : TM < KBM_CARRY ? TM : KBM_CARRY;
     float cnu[NC > 0 ? NC : 1], cs[NC > 0 ? NC : 1];
 #pragma unroll
@@ -544,12 +544,12 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
         // sweep, across chunks, and in the state read back), so v exceeds
         // every index in the list: under the tie rule an equal L keeps the
         // older entry, and ranks_before(L, v, x, i) reduces to L > x.  The
-        // insertion is branch-free (some lane of the wave inserts at almost
-        // every velocity): c_j = (L > kL[j]) is false then true down the
-        // descending list, so slot j takes kL[j] before the insertion point,
-        // L at it and kL[j-1] after it.  A lane that does not insert uses
-        // L = -inf, for which every c_j is false.  Once the list holds good
-        // entries most velocities insert in no lane and skip the block.
+        // insertion itself is branch-free: c_j = (L > kL[j]) is false then
+        // true down the descending list, so slot j takes kL[j] before the
+        // insertion point, L at it and kL[j-1] after it; a lane that does
+        // not insert uses L = -inf, for which every c_j is false.  Once the
+        // lists hold good entries most velocities insert in no lane of the
+        // wave, which then skips the block.
         const bool obs_ok = (CLEAN && fast) || nv >= a.min_obs;
         const float xL = __builtin_elementwise_minimum(
             (obs_ok && isfinite(sc.L)) ? sc.L : -INFINITY, gate);
