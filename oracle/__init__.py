@@ -58,6 +58,13 @@ def _load():
         lib.kbmo_search.argtypes = [i32, i32, i32, P, P, P, i32, P, i32, i32,
                                     i32, f64, f64, f64, f64, i32, i32, i32,
                                     i32, P, P, P, P, P, P]
+        lib.kbmo_search_ex.argtypes = [i32, i32, i32, P, P, P, i32, P, i32, i32,
+                                       i32, i32, f64, f64, f64, f64, i32, i32, i32,
+                                       i32, P, P, P, P, P, P]
+        lib.kbmo_sigmag_ex.argtypes = [i64, i32, P, P, P, i32, i32, f64, f64, f64,
+                                       f64, P, P, P, P]
+        lib.kbmo_eval_grid.argtypes = [i32, i32, i32, P, P, P, i64, P, P, i32, i32,
+                                       i32, f64, f64, f64, f64, P, P, P, P, P, P, P]
         lib.kbmo_refine.argtypes = [i32, i32, i32, P, P, P, i64, P, P, P, P,
                                     P, P, P]
         lib.kbmo_score.argtypes = [i32, i32, i32, P, P, P, i64, P, i32, i32, f64,
@@ -107,12 +114,26 @@ def offsets(times, vels):
     return off
 
 
+DECISIONS = {"f32": 0, "f64": 1}
+
+
+def _decision(d):
+    if d not in DECISIONS:
+        raise ValueError(f"decision must be one of {sorted(DECISIONS)}")
+    return DECISIONS[d]
+
+
 def sigmag(psi_curve, phi_curve=None, valid=None, q_lo=0.25, q_hi=0.75,
-           coeff=0.7413, n_sigma=2.0, quantity=0):
+           coeff=0.7413, n_sigma=2.0, quantity=0, decision="f32",
+           want_margin=False):
     """Standalone sigma_G filter over ``[n][T]`` lightcurves (Section 3.1);
     ``quantity`` 0 filters psi/sqrt(phi) (likelihood), 1 psi/phi (flux).
+    ``decision`` is the precision of the keep decision ("f32": binary32,
+    "f64": binary64).
 
-    Returns (keep uint64 [n], lh float64 [n])."""
+    Returns (keep uint64 [n], lh float64 [n]), plus, with ``want_margin``,
+    the FP64 margins |nu_i - x_50| - thr ``[n][T]`` (NaN where an epoch does
+    not take part) and the largest |nu_i| per lightcurve ``[n]``."""
     lib = _load()
     ps = _c(psi_curve, np.float32)
     n, T = ps.shape
@@ -120,18 +141,25 @@ def sigmag(psi_curve, phi_curve=None, valid=None, q_lo=0.25, q_hi=0.75,
     va = _c(valid, np.uint8)
     keep = np.empty(n, np.uint64)
     lh = np.empty(n, np.float64)
-    rc = lib.kbmo_sigmag_q(n, T, _p(ps), _p(ph), _p(va), int(quantity), q_lo,
-                           q_hi, coeff, n_sigma, _p(keep), _p(lh))
+    margin = np.empty((n, T), np.float64) if want_margin else None
+    numax = np.empty(n, np.float64) if want_margin else None
+    rc = lib.kbmo_sigmag_ex(n, T, _p(ps), _p(ph), _p(va), int(quantity),
+                            _decision(decision), q_lo, q_hi, coeff, n_sigma,
+                            _p(keep), _p(lh), _p(margin), _p(numax))
     if rc:
         raise ValueError("oracle sigmag: bad arguments")
+    if want_margin:
+        return keep, lh, margin, numax
     return keep, lh
 
 
 def search(psi, phi, times, vels, *, k=8, min_obs=1, sigmag=1, q_lo=0.25,
-           q_hi=0.75, coeff=0.7413, n_sigma=2.0, region=None, **_ignored):
+           q_hi=0.75, coeff=0.7413, n_sigma=2.0, region=None, decision="f32",
+           **_ignored):
     """Exhaustive search over float32 planes.
 
-    ``region = (x_begin, y_begin, x_end, y_end)`` (default: whole image).
+    ``region = (x_begin, y_begin, x_end, y_end)`` (default: whole image);
+    ``decision`` the precision of the sigma_G keep decision ("f32", "f64").
     Returns a dict of ``[Hr][Wr][k]`` arrays: lh (filtered likelihood),
     flux, vel_idx, n_obs, keep, lh_raw."""
     lib = _load()
@@ -149,13 +177,47 @@ def search(psi, phi, times, vels, *, k=8, min_obs=1, sigmag=1, q_lo=0.25,
                n_obs=np.empty((Hr, Wr, k), np.int32),
                keep=np.empty((Hr, Wr, k), np.uint64),
                lh_raw=np.empty((Hr, Wr, k), np.float64))
-    rc = lib.kbmo_search(T, H, W, _p(psi), _p(phi), _p(times), vels.shape[0],
-                         _p(vels), k, min_obs, int(sigmag), q_lo, q_hi, coeff,
-                         n_sigma, x0, y0, x1, y1, _p(out["lh"]),
-                         _p(out["flux"]), _p(out["vel_idx"]), _p(out["n_obs"]),
-                         _p(out["keep"]), _p(out["lh_raw"]))
+    rc = lib.kbmo_search_ex(T, H, W, _p(psi), _p(phi), _p(times), vels.shape[0],
+                            _p(vels), k, min_obs, int(sigmag), _decision(decision),
+                            q_lo, q_hi, coeff, n_sigma, x0, y0, x1, y1, _p(out["lh"]),
+                            _p(out["flux"]), _p(out["vel_idx"]), _p(out["n_obs"]),
+                            _p(out["keep"]), _p(out["lh_raw"]))
     if rc:
         raise ValueError("oracle search: bad arguments (rc=%d)" % rc)
+    return out
+
+
+def eval_grid(psi, phi, times, starts, vels, *, min_obs=1, sigmag=1, q_lo=0.25,
+              q_hi=0.75, coeff=0.7413, n_sigma=2.0, decision="f32",
+              want_margin=False, **_ignored):
+    """Evaluate explicit grid trajectories exactly as the search does:
+    ``starts`` int ``[n][2]`` start pixels (x, y), ``vels`` ``[n][2]``
+    velocities (px/day).  Returns a dict of ``[n]`` arrays lh, flux, keep,
+    n_obs, lh_raw (lh = -inf where the search would drop the trajectory),
+    and with ``want_margin`` the FP64 decision margins ``margin`` [n][T]
+    and ``numax`` [n] (see ``sigmag``)."""
+    lib = _load()
+    psi, phi = _c(psi, np.float32), _c(phi, np.float32)
+    times = _c(times, np.float64)
+    starts = _c(starts, np.int32).reshape(-1, 2)
+    vels = _c(vels, np.float32).reshape(-1, 2)
+    T, H, W = psi.shape
+    n = starts.shape[0]
+    if vels.shape[0] != n:
+        raise ValueError("eval_grid: starts and vels differ in length")
+    out = dict(lh=np.empty(n, np.float64), flux=np.empty(n, np.float64),
+               keep=np.empty(n, np.uint64), n_obs=np.empty(n, np.int32),
+               lh_raw=np.empty(n, np.float64))
+    if want_margin:
+        out["margin"] = np.empty((n, T), np.float64)
+        out["numax"] = np.empty(n, np.float64)
+    rc = lib.kbmo_eval_grid(T, H, W, _p(psi), _p(phi), _p(times), n, _p(starts),
+                            _p(vels), int(min_obs), int(sigmag), _decision(decision),
+                            q_lo, q_hi, coeff, n_sigma, _p(out["lh"]), _p(out["flux"]),
+                            _p(out["keep"]), _p(out["n_obs"]), _p(out["lh_raw"]),
+                            _p(out.get("margin")), _p(out.get("numax")))
+    if rc:
+        raise ValueError("oracle eval_grid: bad arguments")
     return out
 
 

@@ -20,12 +20,16 @@
  *   - the in-line per-pixel top-K of Section 3.2;
  *   - the bilinear refinement objective and its analytic gradient.
  *
- * One deliberate non-FP64 step: the sigma_G keep decision (the per-epoch
- * nu_i, the order statistics, sigma_G, the threshold and the comparison) is
- * evaluated in IEEE binary32 with correctly rounded division and square
- * root.  The paper does not fix a precision; the GPU kernel takes this
- * decision in binary32, so both sides take it in binary32 and the keep
- * masks can be compared bit for bit.  Sums and likelihoods stay FP64.
+ * The sigma_G keep decision (the per-epoch nu_i, the order statistics,
+ * sigma_G, the threshold and the comparison) can be taken in two
+ * precisions.  The paper fixes none.  "binary64" (decision 1) is the plain
+ * FP64 definition.  "binary32" (decision 0, the default of the legacy entry
+ * points) takes the same steps in IEEE binary32 with correctly rounded
+ * division and square root: the GPU kernel decides in binary32, so keep
+ * masks of the two can be compared bit for bit, while the FP64 decision
+ * with its per-epoch margins |nu_i - x_50| - thr certifies that every bit
+ * where binary32 and FP64 disagree lies within binary32 rounding of the
+ * threshold.  Sums and likelihoods stay FP64 in both modes.
  *
  * Build: gcc -O2 -fPIC -shared -fopenmp -ffp-contract=off (no fast-math).
  */
@@ -137,6 +141,7 @@ void kbmo_offsets(int32_t T, const double *times, int32_t V, const float *vel,
 typedef struct {
     double q_lo, q_hi, coeff, n_sigma;
     int quantity; /* filtered value per epoch: 0 psi/sqrt(phi), 1 psi/phi */
+    int decision; /* precision of the keep decision: 0 binary32, 1 binary64 */
 } sg_params;
 
 /* Nearest-rank selection: the q-quantile of n sorted values is the value
@@ -152,10 +157,16 @@ static int cmp_f32(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-/* Keep mask over the participating epochs (part[i] != 0).  Binary32
- * throughout, matching the kernel's precision for this decision. */
-static uint64_t sigmag_keep(int T, const float *ps, const float *ph,
-                            const int *part, const sg_params *p)
+static int cmp_f64(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Keep mask over the participating epochs (part[i] != 0), every step in
+ * binary32. */
+static uint64_t sigmag_keep32(int T, const float *ps, const float *ph,
+                              const int *part, const sg_params *p)
 {
     float nu[KBMO_MAX_T], s[KBMO_MAX_T];
     int n = 0;
@@ -177,6 +188,54 @@ static uint64_t sigmag_keep(int T, const float *ps, const float *ph,
     return keep;
 }
 
+/* The same decision in binary64 (Eqs. 1-5 evaluated as written).  When
+ * margin != NULL it receives, per epoch, |nu_i - x_50| - thr (negative:
+ * kept with room to spare; NaN for epochs that do not participate), and
+ * *numax the largest |nu_i| of the lightcurve (0 when none participates). */
+static uint64_t sigmag_keep64(int T, const float *ps, const float *ph,
+                              const int *part, const sg_params *p,
+                              double *margin, double *numax)
+{
+    double nu[KBMO_MAX_T], s[KBMO_MAX_T];
+    double big = 0.0;
+    int n = 0;
+    for (int i = 0; i < T; ++i) {
+        if (margin) margin[i] = NAN;
+        if (!part[i]) continue;
+        nu[i] = p->quantity ? (double)ps[i] / (double)ph[i]
+                            : (double)ps[i] / sqrt((double)ph[i]);
+        s[n++] = nu[i];
+        if (fabs(nu[i]) > big) big = fabs(nu[i]);
+    }
+    if (numax) *numax = big;
+    if (n == 0) return 0;
+    qsort(s, (size_t)n, sizeof(double), cmp_f64);
+    const double x_lo = s[quantile_rank(p->q_lo, n)];
+    const double x_md = s[quantile_rank(0.5, n)];
+    const double x_hi = s[quantile_rank(p->q_hi, n)];
+    const double sigma_g = p->coeff * (x_hi - x_lo);
+    const double thr = p->n_sigma * sigma_g;
+    uint64_t keep = 0;
+    for (int i = 0; i < T; ++i) {
+        if (!part[i]) continue;
+        const double d = fabs(nu[i] - x_md);
+        if (d <= thr) keep |= (uint64_t)1 << i;
+        if (margin) margin[i] = d - thr;
+    }
+    return keep;
+}
+
+/* Keep mask in the precision p->decision selects; the FP64 margins are
+ * written when asked for, whichever precision decides. */
+static uint64_t sigmag_keep(int T, const float *ps, const float *ph,
+                            const int *part, const sg_params *p,
+                            double *margin, double *numax)
+{
+    if (p->decision) return sigmag_keep64(T, ps, ph, part, p, margin, numax);
+    if (margin || numax) sigmag_keep64(T, ps, ph, part, p, margin, numax);
+    return sigmag_keep32(T, ps, ph, part, p);
+}
+
 static int usable(float ps, float ph)
 {
     return ph > 0.0f && isfinite(ph) && isfinite(ps);
@@ -186,14 +245,17 @@ static int usable(float ps, float ph)
  * means unit weights (the values in psi are filtered directly).  The
  * filtered per-epoch value is psi/sqrt(phi) (quantity 0, the likelihood) or
  * psi/phi (quantity 1, the flux).  lh = Psi'/sqrt(Phi') over the kept
- * epochs, -inf when nothing participates. */
-int kbmo_sigmag_q(int64_t n, int32_t T, const float *psi, const float *phi,
-                  const uint8_t *valid, int32_t quantity, double q_lo,
-                  double q_hi, double coeff, double n_sigma, uint64_t *keep,
-                  double *lh)
+ * epochs, -inf when nothing participates.  decision: 0 binary32, 1 binary64.
+ * margin ([n][T]) and numax ([n]) are optional: the FP64 margins of the
+ * decision and the largest |nu_i| per lightcurve (see sigmag_keep64). */
+int kbmo_sigmag_ex(int64_t n, int32_t T, const float *psi, const float *phi,
+                   const uint8_t *valid, int32_t quantity, int32_t decision,
+                   double q_lo, double q_hi, double coeff, double n_sigma,
+                   uint64_t *keep, double *lh, double *margin, double *numax)
 {
     if (T <= 0 || T > KBMO_MAX_T || (quantity != 0 && quantity != 1)) return 1;
-    const sg_params p = {q_lo, q_hi, coeff, n_sigma, quantity};
+    if (decision != 0 && decision != 1) return 1;
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma, quantity, decision};
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < n; ++c) {
         float ps[KBMO_MAX_T], ph[KBMO_MAX_T];
@@ -203,7 +265,9 @@ int kbmo_sigmag_q(int64_t n, int32_t T, const float *psi, const float *phi,
             ph[i] = phi ? phi[c * T + i] : 1.0f;
             part[i] = (!valid || valid[c * T + i]) && usable(ps[i], ph[i]);
         }
-        const uint64_t kp = sigmag_keep(T, ps, ph, part, &p);
+        const uint64_t kp = sigmag_keep(T, ps, ph, part, &p,
+                                        margin ? margin + c * T : NULL,
+                                        numax ? numax + c : NULL);
         double sp = 0.0, sf = 0.0;
         for (int i = 0; i < T; ++i)
             if (kp >> i & 1) {
@@ -214,6 +278,15 @@ int kbmo_sigmag_q(int64_t n, int32_t T, const float *psi, const float *phi,
         if (lh) lh[c] = sf > 0.0 ? sp / sqrt(sf) : -INFINITY;
     }
     return 0;
+}
+
+int kbmo_sigmag_q(int64_t n, int32_t T, const float *psi, const float *phi,
+                  const uint8_t *valid, int32_t quantity, double q_lo,
+                  double q_hi, double coeff, double n_sigma, uint64_t *keep,
+                  double *lh)
+{
+    return kbmo_sigmag_ex(n, T, psi, phi, valid, quantity, 0, q_lo, q_hi,
+                          coeff, n_sigma, keep, lh, NULL, NULL);
 }
 
 int kbmo_sigmag(int64_t n, int32_t T, const float *psi, const float *phi,
@@ -235,22 +308,89 @@ static int ranks_before(double la, int ia, double lb, int ib)
     return la > lb || (la == lb && ia < ib);
 }
 
-int kbmo_search(int32_t T, int32_t H, int32_t W, const float *psi,
-                const float *phi, const double *times, int32_t V,
-                const float *vel, int32_t K, int32_t min_obs, int32_t sigmag,
-                double q_lo, double q_hi, double coeff, double n_sigma,
-                int32_t x_begin, int32_t y_begin, int32_t x_end, int32_t y_end,
-                double *out_lh, double *out_flux, int32_t *out_vidx,
-                int32_t *out_nobs, uint64_t *out_keep, double *out_lh_raw)
+typedef struct {
+    double lh, flux, lh_raw;
+    uint64_t keep;
+    int n_obs;
+} traj_result;
+
+/* One trajectory from start pixel (x, y) with integer offsets off[i][2]
+ * per epoch (Section 3): an epoch is usable when its pixel lies in the
+ * image and carries finite psi, phi with phi > 0; Psi, Phi and n_obs run
+ * over the usable epochs; then the filter (if on) and L' = Psi'/sqrt(Phi')
+ * over the kept epochs.  Returns 1 when the trajectory stands (n_obs >=
+ * min_obs, kept phi > 0, finite L'), else 0; n_obs is always set. */
+static int eval_traj(int T, int H, int W, const float *psi, const float *phi,
+                     int x, int y, const int32_t *off, int min_obs,
+                     int sigmag, const sg_params *p, traj_result *r,
+                     double *margin, double *numax)
+{
+    const size_t plane = (size_t)H * W;
+    float ps[KBMO_MAX_T], ph[KBMO_MAX_T];
+    int part[KBMO_MAX_T];
+    int n = 0;
+    double sp = 0.0, sf = 0.0;
+    uint64_t valid = 0;
+    for (int i = 0; i < T; ++i) {
+        const int xx = x + off[2 * i + 0];
+        const int yy = y + off[2 * i + 1];
+        part[i] = 0;
+        ps[i] = 0.0f;
+        ph[i] = 0.0f;
+        if (margin) margin[i] = NAN;
+        if (xx < 0 || xx >= W || yy < 0 || yy >= H) continue;
+        const size_t q = (size_t)i * plane + (size_t)yy * W + xx;
+        if (!usable(psi[q], phi[q])) continue;
+        ps[i] = psi[q];
+        ph[i] = phi[q];
+        part[i] = 1;
+        valid |= (uint64_t)1 << i;
+        ++n;
+        sp += (double)ps[i];
+        sf += (double)ph[i];
+    }
+    r->n_obs = n;
+    if (numax) *numax = 0.0;
+    if (n == 0 || n < min_obs || !(sf > 0.0)) return 0;
+    uint64_t keep = valid;
+    double kp_s = sp, kf_s = sf;
+    if (sigmag) {
+        keep = sigmag_keep(T, ps, ph, part, p, margin, numax);
+        kp_s = 0.0;
+        kf_s = 0.0;
+        for (int i = 0; i < T; ++i)
+            if (keep >> i & 1) {
+                kp_s += (double)ps[i];
+                kf_s += (double)ph[i];
+            }
+    }
+    if (!(kf_s > 0.0)) return 0;
+    const double l = kp_s / sqrt(kf_s);
+    if (!isfinite(l)) return 0;
+    r->lh = l;
+    r->flux = kp_s / kf_s;
+    r->lh_raw = sp / sqrt(sf);
+    r->keep = keep;
+    return 1;
+}
+
+int kbmo_search_ex(int32_t T, int32_t H, int32_t W, const float *psi,
+                   const float *phi, const double *times, int32_t V,
+                   const float *vel, int32_t K, int32_t min_obs, int32_t sigmag,
+                   int32_t decision, double q_lo, double q_hi, double coeff,
+                   double n_sigma, int32_t x_begin, int32_t y_begin,
+                   int32_t x_end, int32_t y_end, double *out_lh,
+                   double *out_flux, int32_t *out_vidx, int32_t *out_nobs,
+                   uint64_t *out_keep, double *out_lh_raw)
 {
     if (T <= 0 || T > KBMO_MAX_T || K <= 0 || V <= 0) return 1;
     if (x_end < x_begin || y_end < y_begin) return 1;
+    if (decision != 0 && decision != 1) return 1;
     const int Wr = x_end - x_begin, Hr = y_end - y_begin;
     int32_t *off = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)V * T);
     if (!off) return 3;
     kbmo_offsets(T, times, V, vel, off);
-    const sg_params p = {q_lo, q_hi, coeff, n_sigma, 0};
-    const size_t plane = (size_t)H * W;
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma, 0, decision};
 
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
     for (int ry = 0; ry < Hr; ++ry) {
@@ -270,48 +410,13 @@ int kbmo_search(int32_t T, int32_t H, int32_t W, const float *psi,
                 if (lr) lr[s] = -INFINITY;
             }
             for (int v = 0; v < V; ++v) {
-                float ps[KBMO_MAX_T], ph[KBMO_MAX_T];
-                int part[KBMO_MAX_T];
-                int n = 0;
-                double sp = 0.0, sf = 0.0;
-                uint64_t valid = 0;
-                for (int i = 0; i < T; ++i) {
-                    const int xx = x + off[((size_t)v * T + i) * 2 + 0];
-                    const int yy = y + off[((size_t)v * T + i) * 2 + 1];
-                    part[i] = 0;
-                    ps[i] = 0.0f;
-                    ph[i] = 0.0f;
-                    if (xx < 0 || xx >= W || yy < 0 || yy >= H) continue;
-                    const size_t q = (size_t)i * plane + (size_t)yy * W + xx;
-                    if (!usable(psi[q], phi[q])) continue;
-                    ps[i] = psi[q];
-                    ph[i] = phi[q];
-                    part[i] = 1;
-                    valid |= (uint64_t)1 << i;
-                    ++n;
-                    sp += (double)ps[i];
-                    sf += (double)ph[i];
-                }
-                if (n == 0 || n < min_obs || !(sf > 0.0)) continue;
-                const double l_raw = sp / sqrt(sf);
-                uint64_t keep = valid;
-                double kp_s = sp, kf_s = sf;
-                if (sigmag) {
-                    keep = sigmag_keep(T, ps, ph, part, &p);
-                    kp_s = 0.0;
-                    kf_s = 0.0;
-                    for (int i = 0; i < T; ++i)
-                        if (keep >> i & 1) {
-                            kp_s += (double)ps[i];
-                            kf_s += (double)ph[i];
-                        }
-                }
-                if (!(kf_s > 0.0)) continue;
-                const double l = kp_s / sqrt(kf_s);
-                if (!isfinite(l)) continue;
-                if (!ranks_before(l, v, lh[K - 1], vi[K - 1])) continue;
+                traj_result t;
+                if (!eval_traj(T, H, W, psi, phi, x, y, off + (size_t)v * T * 2,
+                               min_obs, sigmag, &p, &t, NULL, NULL))
+                    continue;
+                if (!ranks_before(t.lh, v, lh[K - 1], vi[K - 1])) continue;
                 int s = K - 1;
-                while (s > 0 && ranks_before(l, v, lh[s - 1], vi[s - 1])) {
+                while (s > 0 && ranks_before(t.lh, v, lh[s - 1], vi[s - 1])) {
                     lh[s] = lh[s - 1];
                     fl[s] = fl[s - 1];
                     vi[s] = vi[s - 1];
@@ -320,16 +425,69 @@ int kbmo_search(int32_t T, int32_t H, int32_t W, const float *psi,
                     if (lr) lr[s] = lr[s - 1];
                     --s;
                 }
-                lh[s] = l;
-                fl[s] = kp_s / kf_s;
+                lh[s] = t.lh;
+                fl[s] = t.flux;
                 vi[s] = v;
-                no[s] = n;
-                kp[s] = keep;
-                if (lr) lr[s] = l_raw;
+                no[s] = t.n_obs;
+                kp[s] = t.keep;
+                if (lr) lr[s] = t.lh_raw;
             }
         }
     }
     free(off);
+    return 0;
+}
+
+int kbmo_search(int32_t T, int32_t H, int32_t W, const float *psi,
+                const float *phi, const double *times, int32_t V,
+                const float *vel, int32_t K, int32_t min_obs, int32_t sigmag,
+                double q_lo, double q_hi, double coeff, double n_sigma,
+                int32_t x_begin, int32_t y_begin, int32_t x_end, int32_t y_end,
+                double *out_lh, double *out_flux, int32_t *out_vidx,
+                int32_t *out_nobs, uint64_t *out_keep, double *out_lh_raw)
+{
+    return kbmo_search_ex(T, H, W, psi, phi, times, V, vel, K, min_obs, sigmag,
+                          0, q_lo, q_hi, coeff, n_sigma, x_begin, y_begin,
+                          x_end, y_end, out_lh, out_flux, out_vidx, out_nobs,
+                          out_keep, out_lh_raw);
+}
+
+/* Explicit grid trajectories: n pairs of an integer start pixel
+ * (start[j] = x, y) and a velocity (vel[j] = vx, vy, px/day), each
+ * evaluated exactly as the search evaluates it (same offsets, usable
+ * epochs, filter and L').  A trajectory the search would drop gets
+ * lh = lh_raw = -inf, flux 0, keep 0; n_obs is always reported.  margin
+ * ([n][T]) and numax ([n]) are optional: the FP64 margins of the filter
+ * decision (NaN where an epoch does not take part, or for a dropped
+ * trajectory, or with the filter off). */
+int kbmo_eval_grid(int32_t T, int32_t H, int32_t W, const float *psi,
+                   const float *phi, const double *times, int64_t n,
+                   const int32_t *start, const float *vel, int32_t min_obs,
+                   int32_t sigmag, int32_t decision, double q_lo, double q_hi,
+                   double coeff, double n_sigma, double *out_lh,
+                   double *out_flux, uint64_t *out_keep, int32_t *out_nobs,
+                   double *out_lh_raw, double *margin, double *numax)
+{
+    if (T <= 0 || T > KBMO_MAX_T || n < 0) return 1;
+    if (decision != 0 && decision != 1) return 1;
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma, 0, decision};
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        int32_t off[2 * KBMO_MAX_T];
+        kbmo_offsets(T, times, 1, vel + 2 * j, off);
+        traj_result t;
+        double *mg = margin ? margin + j * T : NULL;
+        const int ok = eval_traj(T, H, W, psi, phi, start[2 * j], start[2 * j + 1],
+                                 off, min_obs, sigmag, &p, &t, mg,
+                                 numax ? numax + j : NULL);
+        out_nobs[j] = t.n_obs;
+        out_lh[j] = ok ? t.lh : -INFINITY;
+        out_flux[j] = ok ? t.flux : 0.0;
+        out_keep[j] = ok ? t.keep : 0;
+        if (out_lh_raw) out_lh_raw[j] = ok ? t.lh_raw : -INFINITY;
+        if (!ok && mg)
+            for (int i = 0; i < T; ++i) mg[i] = NAN;
+    }
     return 0;
 }
 
@@ -353,7 +511,7 @@ int kbmo_score(int32_t T, int32_t H, int32_t W, const float *psi,
                int32_t *out_nobs, double *out_lh_raw)
 {
     if (T <= 0 || T > KBMO_MAX_T || n < 0) return 1;
-    const sg_params p = {q_lo, q_hi, coeff, n_sigma, 0};
+    const sg_params p = {q_lo, q_hi, coeff, n_sigma, 0, 0};
     const double t0 = earliest(T, times);
     const size_t plane = (size_t)H * W;
 
@@ -393,7 +551,7 @@ int kbmo_score(int32_t T, int32_t H, int32_t W, const float *psi,
         uint64_t keep = valid;
         double kp_s = sp, kf_s = sf;
         if (sigmag) {
-            keep = sigmag_keep(T, ps, ph, part, &p);
+            keep = sigmag_keep(T, ps, ph, part, &p, NULL, NULL);
             kp_s = 0.0;
             kf_s = 0.0;
             for (int i = 0; i < T; ++i)

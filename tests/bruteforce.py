@@ -59,7 +59,26 @@ def sigmag_keep(values_psi, values_phi, q_lo, q_hi, coeff, n_sigma):
     return [bool(abs(F32(x - x_md)) <= thr) for x in nu]
 
 
-def trajectory(psi, phi, times, vel, x, y, sigmag, q_lo, q_hi, coeff, n_sigma):
+def sigmag_keep64(values_psi, values_phi, q_lo, q_hi, coeff, n_sigma):
+    """Keep flags for a list of (psi, phi) samples, the decision taken in
+    Python floats (binary64) straight from Eqs. 1-5: nu = psi/sqrt(phi),
+    nearest-rank quantiles of the sorted values, sigma_G = C (x_hi - x_lo),
+    keep when |nu - x_50| <= n sigma_G."""
+    nu = [float(a) / math.sqrt(float(b)) for a, b in zip(values_psi, values_phi)]
+    n = len(nu)
+    if n == 0:
+        return []
+    s = sorted(nu)
+
+    def q(qq):
+        return s[int(math.floor(qq * (n - 1) + 0.5))]
+
+    thr = n_sigma * (coeff * (q(q_hi) - q(q_lo)))
+    return [abs(x - q(0.5)) <= thr for x in nu]
+
+
+def trajectory(psi, phi, times, vel, x, y, sigmag, q_lo, q_hi, coeff, n_sigma,
+               decision="f32"):
     """Evaluate one trajectory; returns None when it has no usable epoch."""
     T, H, W = psi.shape
     t0 = min(times)
@@ -79,7 +98,8 @@ def trajectory(psi, phi, times, vel, x, y, sigmag, q_lo, q_hi, coeff, n_sigma):
         return None
     lraw = math.fsum(ps) / math.sqrt(math.fsum(ph))
     if sigmag:
-        kf = sigmag_keep(ps, ph, q_lo, q_hi, coeff, n_sigma)
+        rule = sigmag_keep64 if decision == "f64" else sigmag_keep
+        kf = rule(ps, ph, q_lo, q_hi, coeff, n_sigma)
     else:
         kf = [True] * len(idx)
     kp = [a for a, k in zip(ps, kf) if k]
@@ -129,7 +149,7 @@ def trajectory_real(psi, phi, times, prm, sigmag, q_lo, q_hi, coeff, n_sigma):
 
 
 def search(psi, phi, times, vels, k, min_obs, sigmag=1, q_lo=0.25, q_hi=0.75,
-           coeff=0.7413, n_sigma=2.0, region=None):
+           coeff=0.7413, n_sigma=2.0, region=None, decision="f32"):
     T, H, W = psi.shape
     x0, y0, x1, y1 = region or (0, 0, W, H)
     out = dict(lh=np.full((y1 - y0, x1 - x0, k), -np.inf),
@@ -143,7 +163,7 @@ def search(psi, phi, times, vels, k, min_obs, sigmag=1, q_lo=0.25, q_hi=0.75,
             cands = []
             for v in range(len(vels)):
                 r = trajectory(psi, phi, times, vels[v], x, y, sigmag, q_lo,
-                               q_hi, coeff, n_sigma)
+                               q_hi, coeff, n_sigma, decision)
                 if r is None or r["n_obs"] < min_obs or not math.isfinite(r["lh"]):
                     continue
                 cands.append((-r["lh"], v, r))

@@ -103,3 +103,35 @@ def test_stamps_noise_free_source(kbm, oracle_mod):
     assert abs(m[1]) < 1e-12 and abs(m[2]) < 1e-12 and abs(m[3]) < 1e-12
     assert m[4] == pytest.approx(xx, rel=1e-9) and m[5] == pytest.approx(xx, rel=1e-9)
     assert bool(got["passed"][0])
+
+
+def test_moment_limits_strict_on_gpu(kbm, oracle_mod):
+    """Coadds whose moments sit exactly on a limit (x = 0.5, xy = 1.5,
+    xx = yy = 36.5; every sum exact in binary64 in any order) fail the cut
+    on the GPU as in the oracle, and their twins nudged inside pass.  Three
+    identical epochs and a static trajectory make the median coadd the
+    pattern itself."""
+    from tests.test_oracle_stamps import _limit_stamps
+    pats = []
+    for _, s in _limit_stamps():
+        pats.append(s)
+        s2 = s.copy()
+        s2[10, 10] += 1e-3
+        pats.append(s2)
+    T, r = 3, 10
+    W = 21 * len(pats) + 10
+    H = 31
+    img = np.zeros((H, W), np.float32)
+    prm = []
+    for j, s in enumerate(pats):
+        x0 = 5 + 21 * j
+        img[5:26, x0:x0 + 21] = s.astype(np.float32)
+        prm.append([x0 + 10, 15, 0.0, 0.0])
+    sci = np.ascontiguousarray(np.broadcast_to(img, (T, H, W)))
+    var = np.ones((T, H, W), np.float32)
+    times = np.array([0.0, 0.01, 0.02])
+    prm = np.array(prm, np.float32)
+    got = kbm.stamps(_cu(sci), _cu(var), None, times, _cu(prm), radius=r)
+    ref, m_ref, p_ref = _compare(oracle_mod, got, sci, var, None, times, prm, r)
+    assert list(p_ref) == [False, True] * (len(pats) // 2)
+    assert np.array_equal(got["passed"].cpu().numpy(), p_ref)

@@ -119,3 +119,55 @@ def test_stamp_outside_image_is_zero(oracle_mod):
     s = oracle_mod.stamps(sci, var, None, [0, 1, 2], prm, radius=3)
     assert np.all(s[0] == 0)
     assert s[1][3, 3] == 1 and s[1].sum() == 49.0
+
+
+def _limit_stamps(r=10):
+    """Coadds whose moments sit exactly on a limit of the cut (every value
+    and sum below is exact in binary64):
+      * x = 0.5: equal mass at dx = 0 and dx = +1 on the centre row;
+      * xx = 36.5: mass 63.5 at dx = -6 and +6 and 0.5 at dx = -10 and +10
+        (total 128): (127 * 36 + 100) / 128 = 36.5;
+      * yy = 36.5: the transpose of the previous one;
+      * xy = 1.5: mass 7.5 at (dx, dy) = (1, 1) and (-1, -1) and 0.5 at
+        (3, 3) and (-3, -3) (total 16): (15 * 1 + 1 * 9) / 16 = 1.5, with
+        x = y = 0 and xx = yy = 1.5."""
+    k = 2 * r + 1
+    out = []
+    a = np.zeros((k, k))
+    a[r, r] = a[r, r + 1] = 1.0
+    out.append(("x", a))
+    b = np.zeros((k, k))
+    b[r, r - 6] = b[r, r + 6] = 63.5
+    b[r, r - 10] = b[r, r + 10] = 0.5
+    out.append(("xx", b))
+    by = b.T.copy()
+    out.append(("yy", by))
+    c = np.zeros((k, k))
+    c[r + 1, r + 1] = c[r - 1, r - 1] = 7.5
+    c[r + 3, r + 3] = c[r - 3, r - 3] = 0.5
+    out.append(("xy", c))
+    return out
+
+
+def test_moment_limits_are_strict(oracle_mod):
+    """Section 3.3 asks for moments strictly below their limits: a coadd
+    whose x moment is exactly 0.5, or whose xx or yy is exactly 36.5, fails
+    the cut, as does one whose xy is exactly 1.5, and the same coadd nudged
+    just inside passes."""
+    for name, s in _limit_stamps():
+        m = oracle_mod.stamp_moments(s)
+        col = {"x": 1, "xy": 3, "xx": 4, "yy": 5}[name]
+        lim = {"x": 0.5, "xy": 1.5, "xx": 36.5, "yy": 36.5}[name]
+        assert m[col] == lim, (name, m)
+        assert not bool(oracle_mod.stamp_pass(m)), name
+        # nudge: a little more mass at the centre pulls the moment inside
+        s2 = s.copy()
+        s2[10, 10] += 1e-6
+        m2 = oracle_mod.stamp_moments(s2)
+        assert m2[col] < lim
+        assert bool(oracle_mod.stamp_pass(m2)), (name, m2)
+    # |x| with a negative moment exactly at the limit fails as well
+    s = np.zeros((21, 21))
+    s[10, 10] = s[10, 9] = 1.0
+    m = oracle_mod.stamp_moments(s)
+    assert m[1] == -0.5 and not bool(oracle_mod.stamp_pass(m))
