@@ -15,11 +15,15 @@ Inputs are synthetic (seeded, shaped like the paper's DECam NEO difference
 images) and resident in HBM before timing starts.
 
 Prints one JSON line.  The metric counts trajectory-epoch evaluations
-nominally, W * H * V * T per search, whatever the validity or pruning.
+nominally, W * H * V * T per search, whatever the validity or pruning; the
+line also gives the evaluated and valid shares, the roofline of the search
+kernel on two bases (operations against the VALU peak, gathered bytes
+against the LDS bandwidth), the FP64 oracle timed on the host, and, unless
+--no-extras, the records of the 62-stack batched workload and of the full
+pipeline (coarse grid + refinement against a dense grid), each run once
+after one warm-up.
 """
 import argparse
-import hashlib
-import re
 import json
 import math
 import os
@@ -33,36 +37,29 @@ sys.path.insert(0, ROOT)
 # operations: 256 CUs x 64 lanes/clk x 2.4 GHz.  The published 157.3 TFLOP/s
 # counts an FMA as two flops and packed FP32 as two lanes.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# LDS bandwidth of MI355X: 256 CUs x 128 B/clk x 2.4 GHz (the level at which
+# a trajectory-epoch's 8-byte sample is gathered in the roofline's model).
+LDS_PEAK_GBS = 256 * 128 * 2.4e9 / 1e9
+GATHER_BYTES = 8          # one (nu, sqrt(phi)) float pair per trajectory-epoch
 
-
-# Kernel sources of the persistent search kernel; a traffic figure taken
-# with hardware counters is reported only while these are unchanged.
-KERNEL_SOURCES = ["batch_kernels.h", "batch_nw1.hip", "batch_nw4.hip", "batch_nw1c.hip",
-                  "batch_nw4c.hip",
-                  "search_kernels.h", "kbm_internal.h", "sortnet.h"]
+# Hardware-counter figures of the persistent kernel are reported only while
+# the library's sources and flags hash to the id recorded with them.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_kernel_c2_counters.md")
 N_CANDIDATES = 100_000
 REFINE_STEPS = 50
 
 
 def kernel_source_hash():
-    """Hash of the persistent kernel's sources with comments and blank
-    lines removed (a comment edit does not invalidate measured figures)."""
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2109_03296_amd", "csrc", f)) as fh:
-            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
-        for line in text.splitlines():
-            code = line.split("//", 1)[0].rstrip()
-            if code:
-                h.update(code.encode() + b"\n")
-    return h.hexdigest()[:16]
+    """Build id of the library sources (comments excluded) and flags."""
+    from paper_2109_03296_amd import build
+    return build.source_hash()
 
 
 def measured_counters():
     """Figures of the persistent kernel from the committed counter summary
-    (HBM bytes per launch, VALU busy fraction, L1 accesses per CU-cycle), or
-    {} when it is missing or was taken on other kernel sources."""
+    (HBM bytes per launch, VALU busy fraction, data-return busy fraction, L1
+    accesses per CU-cycle), or {} when it is missing or was taken on other
+    sources."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -75,7 +72,7 @@ def measured_counters():
     if vals.get("kernel_source_hash") != kernel_source_hash():
         return {}
     out = {}
-    for k in ("hbm_bytes_per_launch", "valu_busy", "l1_accesses_per_cu_cycle"):
+    for k in ("hbm_bytes_per_launch", "valu_busy", "td_busy", "l1_accesses_per_cu_cycle"):
         try:
             out[k] = float(vals[k])
         except (KeyError, ValueError):
@@ -87,64 +84,155 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def search_alg_ops(T, sigmag):
-    """Algorithmic FP32 operations per trajectory-epoch of the search.
+def select_lower_bound(n, ranks):
+    """Comparisons any comparison-based method needs to select the order
+    statistics at 0-based ``ranks`` of n values: selecting the i-th smallest
+    (1-based) needs at least n - 1 + min(i - 1, n - i) comparisons (the
+    adversary argument: n - 1 comparisons to tie every other value to the
+    answer, and min(i - 1, n - i) more that cannot serve both sides); more
+    ranks need at least as many."""
+    return max(n - 1 + min(r, n - 1 - r) for r in ranks)
 
-    Plain path: the two running sums (Psi, Phi).  With sigma_G, per epoch:
-    its share of the order statistics (ceil(log2 T) comparisons, the
-    information-theoretic comparison count per element of a sort), the
-    distance to the median and the threshold test (2), and the two kept
-    sums (2).  nu = psi/sqrt(phi) belongs to the pixel-epoch, not to the
-    trajectory (it is formed once per pixel-epoch, as is the plane), and the
-    unfiltered sums are needed only for the K results a pixel keeps, so
-    neither is counted per trajectory-epoch."""
+
+def search_alg_ops(T, sigmag, q_lo=0.25, q_hi=0.75):
+    """Algorithmic FP32 operations per trajectory-epoch of the search, a
+    lower bound on what any implementation of the method does.
+
+    Plain search: the two running sums (Psi, Phi).  With sigma_G: the
+    comparisons to select the three order statistics (the lower bound of
+    select_lower_bound, spread over the T epochs), then per epoch the
+    distance to the median and the threshold test (2) and the two kept sums
+    (2).  nu = psi/sqrt(phi) belongs to the pixel-epoch, not to the
+    trajectory, and the unfiltered sums are needed only for the K results a
+    pixel keeps, so neither is counted."""
     if not sigmag:
-        return 2
-    return math.ceil(math.log2(max(T, 2))) + 2 + 2
+        return 2.0
+    ranks = [math.floor(q * (T - 1) + 0.5) for q in (q_lo, 0.5, q_hi)]
+    return select_lower_bound(T, ranks) / T + 4.0
 
 
-def cpu_baseline(st, params, log_fn):
-    """Time the FP64 oracle on a bounded sample of the same workload.
+def valid_fraction(times, vels, W, H, min_obs):
+    """Fraction of the W*H*V grid trajectories with at least min_obs epochs
+    inside the image (offsets floor(v t + 1/2) from the earliest epoch, in
+    FP64), counted exactly: per velocity the start pixels whose epoch i is in
+    the image form a rectangle, and the rectangles' boundaries cut the image
+    into cells of equal coverage.  Plane pixels that are unusable (phi <= 0)
+    would lower it further; the benchmark stacks have none."""
+    import numpy as np
+    t = np.asarray(times, np.float64)
+    t = t - t.min()
+    v = np.asarray(vels, np.float32).astype(np.float64)
+    dx = np.floor(v[:, 0:1] * t[None, :] + 0.5).astype(np.int64)
+    dy = np.floor(v[:, 1:2] * t[None, :] + 0.5).astype(np.int64)
 
-    Sample: the planes of a window of the stack that holds every track of a
-    48 x 48 start-pixel block (full velocity grid), and the search of that
-    block; both rates are extrapolated linearly to the full step."""
+    def cells(d, n):
+        lo = np.clip(-d, 0, n)
+        hi = np.clip(n - d, 0, n)
+        b = np.unique(np.concatenate([[0, n], lo, hi]))
+        inside = (lo[:, None] <= b[None, :-1]) & (b[None, 1:] <= hi[:, None])
+        return np.diff(b), inside.astype(np.float64)
+
+    area = 0.0
+    for j in range(v.shape[0]):
+        lx, X = cells(dx[j], W)
+        ly, Y = cells(dy[j], H)
+        cov = X.T @ Y
+        area += float(lx @ (cov >= min_obs) @ ly)
+    return area / (float(W) * H * v.shape[0])
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(st, params, log_fn, side_all=24, side_one=8, reps=3):
+    """Time the FP64 oracle (binary64 sigma_G decision) on a bounded sample
+    of the same workload.
+
+    Sample: four square start-pixel crops, one on an injected source and
+    three at 1/4, 1/2 and 3/4 of the image diagonal, each against the whole
+    velocity grid, with sigma_G on and off; ``side_all`` px crops on every
+    host thread and ``side_one`` px crops on one thread; each the median of
+    ``reps`` runs.  Planes are computed once per crop over the window its
+    tracks reach.  Rates are per trajectory-epoch; ``value`` extrapolates the
+    all-thread sigma_G-on rate and the planes rate linearly to the full step
+    (planes + search)."""
+    import statistics
+
     import numpy as np
     import oracle
     T, H, W = st.sci.shape
     V = st.vels.shape[0]
-    vx_max = float(np.max(np.abs(st.vels[:, 0]))) * float(st.times.max())
-    vy_max = float(np.max(np.abs(st.vels[:, 1]))) * float(st.times.max())
+    tm = float(np.max(st.times) - np.min(st.times))
+    rx = int(math.ceil(float(np.max(np.abs(st.vels[:, 0]))) * tm)) + 1
+    ry = int(math.ceil(float(np.max(np.abs(st.vels[:, 1]))) * tm)) + 1
     r = st.psf.shape[0] // 2
-    bx = by = 112   # about 10 s of oracle work on a 16-core host
-    wx = min(W, int(bx + vx_max + 2 * r + 4))
-    wy = min(H, int(by + 2 * vy_max + 2 * r + 4))
-    y0 = max(0, H // 2 - wy // 2)
-    sl = (slice(None), slice(y0, y0 + wy), slice(0, wx))
-    sci, var = np.ascontiguousarray(st.sci[sl]), np.ascontiguousarray(st.var[sl])
-    mask = None if st.mask is None else np.ascontiguousarray(st.mask[sl])
-    t0 = time.perf_counter()
-    psi, phi = oracle.planes(sci, var, mask, st.psf)
-    t_planes = time.perf_counter() - t0
-    psi = psi.astype(np.float32)
-    phi = phi.astype(np.float32)
-    sy = wy // 2 - by // 2
-    region = (r + 1, sy, r + 1 + bx, sy + by)
-    t0 = time.perf_counter()
-    oracle.search(psi, phi, st.times, st.vels, region=region, **params)
-    t_search = time.perf_counter() - t0
-    full_planes = t_planes * (T * H * W) / (T * wy * wx)
-    full_search = t_search * (H * W) / (bx * by)
-    value = T * H * W * V / (full_planes + full_search)
-    log_fn(f"cpu oracle: planes {wx}x{wy}x{T} in {t_planes:.2f}s, search "
-           f"{bx}x{by} px x {V} vel in {t_search:.2f}s")
+    src = st.sources[0] if st.sources else dict(x0=W / 2, y0=H / 2)
+    centres = [(int(src["x0"]), int(src["y0"]))] + [
+        (int(W * f), int(H * f)) for f in (0.25, 0.5, 0.75)]
+    full_threads = oracle.num_threads()
+    crops, planes_s, planes_pe = [], 0.0, 0
+    for (cx, cy) in centres:
+        cx = min(max(cx, side_all // 2), W - side_all // 2)
+        cy = min(max(cy, side_all // 2), H - side_all // 2)
+        x0, y0 = max(0, cx - side_all // 2 - rx - r), max(0, cy - side_all // 2 - ry - r)
+        x1, y1 = min(W, cx + side_all // 2 + rx + r), min(H, cy + side_all // 2 + ry + r)
+        sl = (slice(None), slice(y0, y1), slice(x0, x1))
+        mask = None if st.mask is None else np.ascontiguousarray(st.mask[sl])
+        t0 = time.perf_counter()
+        psi, phi = oracle.planes(np.ascontiguousarray(st.sci[sl]),
+                                 np.ascontiguousarray(st.var[sl]), mask, st.psf)
+        planes_s += time.perf_counter() - t0
+        planes_pe += T * (y1 - y0) * (x1 - x0)
+        crops.append((psi.astype(np.float32), phi.astype(np.float32), cx - x0, cy - y0))
+
+    def timed(side, sigmag):
+        runs = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            for (psi, phi, lx, ly) in crops:
+                reg = (lx - side // 2, ly - side // 2, lx - side // 2 + side,
+                       ly - side // 2 + side)
+                oracle.search(psi, phi, st.times, st.vels, region=reg,
+                              **dict(params, sigmag=int(sigmag)), decision="f64")
+            runs.append(time.perf_counter() - t0)
+        sec = statistics.median(runs)
+        return len(crops) * side * side * V * T / sec, sec
+
+    rates = {}
+    try:
+        for sg in (True, False):
+            rates[f"all_threads_sigmag_{'on' if sg else 'off'}"] = timed(side_all, sg)
+        oracle.set_num_threads(1)
+        for sg in (True, False):
+            rates[f"one_thread_sigmag_{'on' if sg else 'off'}"] = timed(side_one, sg)
+    finally:
+        oracle.set_num_threads(full_threads)
+    planes_rate = planes_pe / planes_s
+    search_rate = rates["all_threads_sigmag_on"][0]
+    full = float(W) * H * V * T
+    value = full / (T * H * W / planes_rate + full / search_rate)
+    log_fn("cpu oracle: " + ", ".join(f"{k} {v[0]:.3g}/s" for k, v in rates.items()))
     return {"value": value, "unit": "trajectory-epoch evals/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": (f"planes of a {wx}x{wy}x{T} window of the stack + search of a "
-                       f"{bx}x{by} start-pixel block over all {V} velocities; "
-                       f"extrapolated per pixel-epoch and per trajectory-epoch "
-                       f"to the full {W}x{H} step"),
-            "seconds": t_planes + t_search}
+            "cores": full_threads, "kind": "oracle",
+            "sample": (f"four {side_all}x{side_all} start-pixel crops (one on a source) x "
+                       f"all {V} velocities on {full_threads} threads, sigma_G on, median of "
+                       f"{reps}; planes of the windows their tracks reach; extrapolated per "
+                       f"trajectory-epoch and per pixel-epoch to the full {W}x{H} step"),
+            "cpu_model": _cpu_model(),
+            "rates_traj_epochs_per_s": {k: v[0] for k, v in rates.items()},
+            "one_thread_crop": f"{side_one}x{side_one}",
+            "planes_pixel_epochs_per_s": planes_rate,
+            "decision": "binary64",
+            "seconds": planes_s + sum(v[1] for v in rates.values()) * reps}
 
 
 def main():
@@ -155,7 +243,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true",
-                    help="skip the batched-vs-per-stack comparison after timing")
+                    help="skip the batched-vs-per-stack comparisons after timing")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the 62-stack and full-pipeline "
+                         "records attached to its line")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the persistent kernel's schedule first")
     ap.add_argument("--size", type=str, default=None,
@@ -164,13 +255,14 @@ def main():
                     help="only run a plain device copy of MIB MiB (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--print-hash", action="store_true",
-                    help="print the persistent kernel's source hash and exit")
+                    help="print the library's build id and exit")
     ap.add_argument("--workload", choices=("ccd", "batch62", "pipeline", "respix"),
                     default="ccd",
-                    help="ccd: the DECam-CCD stack (default); batch62: 62 stacks of "
-                         "uneven sizes and epoch counts in one persistent launch; "
-                         "pipeline: 4096^2 x 60 epochs, coarse grid + refinement "
-                         "against a dense grid (recall and time); respix: "
+                    help="ccd: the DECam-CCD stack (default; its line also carries "
+                         "the batch62 and pipeline records unless --no-extras); "
+                         "batch62: 62 stacks of uneven sizes and epoch counts in one "
+                         "persistent launch; pipeline: 4096^2 x 60 epochs, coarse grid "
+                         "+ refinement against a dense grid (recall and time); respix: "
                          "candidates and source survival vs results per pixel, "
                          "in-line filter on and off, with static artifacts")
     args = ap.parse_args()
@@ -194,12 +286,27 @@ def main():
         sys.exit(2)
 
     if args.workload == "batch62":
-        return bench_batch62(args)
+        print(json.dumps(bench_batch62(args, args.steps, args.warmup)), flush=True)
+        return
     if args.workload == "pipeline":
-        return bench_pipeline(args)
+        print(json.dumps(bench_pipeline(args)), flush=True)
+        return
     if args.workload == "respix":
         return bench_respix(args)
+    rec = bench_ccd(args)
+    if not args.no_extras and args.size is None:
+        import torch
+        torch.cuda.empty_cache()
+        log("62-stack batched workload (one warm-up run, one timed run)")
+        rec["batch62"] = bench_batch62(args, 1, 1)
+        torch.cuda.empty_cache()
+        log("full-pipeline workload: dense grid against coarse grid + refinement")
+        rec["pipeline"] = bench_pipeline(args)
+    print(json.dumps(rec), flush=True)
 
+
+def bench_ccd(args):
+    """The default step on the DECam-CCD stack; returns the record."""
     import numpy as np
     import torch
 
@@ -269,6 +376,7 @@ def main():
     if plan.check():
         raise RuntimeError("persistent search: a dependency wait gave up")
     ms_step = (t1 - t0) * 1e3 / args.steps
+    n_eval = plan.evaluated()
 
     def avg(a, b):
         return sum(e[a].elapsed_time(e[b]) for e in stages) / len(stages)
@@ -282,10 +390,14 @@ def main():
 
     traj_epochs = float(W) * H * V * T
     value = traj_epochs / (ms_step / 1e3)
-    ops = search_alg_ops(T, prm["sigmag"])
-    achieved = traj_epochs * ops / (st_ms["search_graph"] / 1e3) / 1e12
+    ops = search_alg_ops(T, prm["sigmag"], prm["q_lo"], prm["q_hi"])
+    t_search = st_ms["search_graph"] / 1e3
+    achieved = n_eval * ops / t_search / 1e12
+    gather = n_eval * GATHER_BYTES / t_search / 1e9
+    log("counting valid trajectories")
+    vfrac = valid_fraction(st.times, st.vels, W, H, prm["min_obs"])
     o = res["n_obs"]
-    valid_frac = float((o >= prm["min_obs"]).float().mean().item())
+    filled = float((o[..., 0] >= prm["min_obs"]).float().mean().item())
     cand = last["cand"]
     lh0 = cand["lh"].double()
     n_cand = int(lh0.numel())
@@ -314,7 +426,12 @@ def main():
                    "candidates": N_CANDIDATES, "refine_steps": REFINE_STEPS},
         "stages_ms": st_ms,
         "schedule": plan.schedule,
-        "top_slot_filled_frac": valid_frac,
+        "trajectories": {
+            "nominal_traj_epochs": traj_epochs,
+            "evaluated_traj_epochs": n_eval,
+            "evaluated_frac": n_eval / traj_epochs,
+            "valid_traj_frac": vfrac,
+            "top_slot_filled_frac": filled},
         "refine": {"candidates": n_cand,
                    "ms_per_adam_step": st_ms["refine"] / REFINE_STEPS,
                    "candidate_epochs_per_s": n_cand * T * REFINE_STEPS /
@@ -326,10 +443,21 @@ def main():
         "roofline": {"bound": "alu", "kernel": "batch_kernel",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "ops_per_traj_epoch": ops, "traffic": counters.get("hbm_bytes_per_launch"),
-                     "counters": {k: counters[k] for k in ("valu_busy", "l1_accesses_per_cu_cycle")
+                     "traffic": counters.get("hbm_bytes_per_launch"),
+                     "ops_per_traj_epoch": ops,
+                     "basis": "evaluated trajectory-epochs x a lower bound on the "
+                              "operations per trajectory-epoch (selection of the "
+                              "order statistics, distance and threshold test, kept sums)",
+                     "counters": {k: counters[k] for k in
+                                  ("valu_busy", "td_busy", "l1_accesses_per_cu_cycle")
                                   if k in counters} or None,
                      "kernel_source_hash": kernel_source_hash()},
+        "roofline_gather": {"bound": "lds", "kernel": "batch_kernel",
+                            "achieved": gather, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                            "frac": gather / LDS_PEAK_GBS,
+                            "bytes_per_traj_epoch": GATHER_BYTES,
+                            "basis": "8 B (nu, sqrt(phi)) per evaluated trajectory-epoch "
+                                     "against the LDS bandwidth"},
     }
     if not args.no_check:
         log("checking the batched results against the per-stack search")
@@ -337,18 +465,22 @@ def main():
         torch.cuda.synchronize()
         same = all(torch.equal(ref[k], res[k]) for k in ref if ref[k] is not None)
         rec["batched_vs_plain"] = {"identical": bool(same)}
+        del ref
     plan.close()
+    del plan, res, psi, phi, sci, var, mask, last, ex_ws
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(st, prm, log)
-    print(json.dumps(rec), flush=True)
+    return rec
 
 
-def bench_batch62(args):
+def bench_batch62(args, steps, warmup):
     """62 independent stacks (sides drawn from 512..4096, T in [10, 30] over
     3 nights, PSF sigma in [1, 2], 1% mask, 20 sources each, 64 x 64
     velocities, K = 8, sigma_G on) searched by one persistent launch.  A
-    step = planes of every stack + one run of the search graph."""
+    step = planes of every stack + one run of the search graph.  Returns the
+    record."""
     import concurrent.futures as cf
 
     import torch
@@ -359,11 +491,12 @@ def bench_batch62(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     specs = synth.make_batched_specs(62)
+    nthr = min(16, os.cpu_count() or 1)
     log(f"generating {len(specs)} stacks ({sum(s['W'] * s['H'] * s['T'] for s in specs) / 1e9:.2f}e9 "
-        f"pixel-epochs) on {min(16, os.cpu_count() or 1)} threads")
+        f"pixel-epochs) on {nthr} threads")
     items, geo = [], []
     t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=nthr) as ex:
         for j, st in enumerate(ex.map(synth.make_batched_stack, specs)):
             sci = torch.from_numpy(st.sci).to(dev)
             var = torch.from_numpy(st.var).to(dev)
@@ -397,31 +530,35 @@ def bench_batch62(args):
         if record:
             spans.append(ev)
 
-    for i in range(args.warmup):
-        log(f"warmup step {i + 1}/{args.warmup}")
+    for i in range(warmup):
+        log(f"warmup step {i + 1}/{warmup}")
         step(False)
         torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
+    log(f"timing {steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(True)
     torch.cuda.synchronize()
-    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
     if plan.check():
         raise RuntimeError("persistent search: a dependency wait gave up")
+    n_eval = plan.evaluated()
     planes_ms = sum(e[0].elapsed_time(e[1]) for e in spans) / len(spans)
     search_ms = sum(e[1].elapsed_time(e[2]) for e in spans) / len(spans)
     te = sum(float(g["W"]) * g["H"] * g["T"] * len(it["vels"]) for g, it in zip(geo, items))
+    # operations of the evaluated trajectory-epochs, stack by stack (the
+    # evaluated share is taken as the batch's overall share)
     ops = sum(float(g["W"]) * g["H"] * g["T"] * len(it["vels"]) * search_alg_ops(g["T"], True)
-              for g, it in zip(geo, items))
+              for g, it in zip(geo, items)) * (n_eval / te)
     achieved = ops / (search_ms / 1e3) / 1e12
+    gather = n_eval * GATHER_BYTES / (search_ms / 1e3) / 1e9
     log(f"step {ms_step:.1f} ms (planes {planes_ms:.1f}, search graph {search_ms:.1f})")
     rec = {
         "metric": "trajectory-epoch evals/s",
         "value": te / (ms_step / 1e3),
         "unit": "trajectory-epoch evals/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "62 stacks, sides from {512,1024,2048,4096}, T in [10,30], "
@@ -430,15 +567,18 @@ def bench_batch62(args):
                    "stacks": len(items), "trajectory_epochs": te},
         "stages_ms": {"planes": planes_ms, "search_graph": search_ms},
         "schedule": plan.schedule,
+        "trajectories": {"nominal_traj_epochs": te, "evaluated_traj_epochs": n_eval,
+                         "evaluated_frac": n_eval / te},
         "roofline": {"bound": "alu", "kernel": "batch_kernel", "achieved": achieved,
                      "peak": VALU_PEAK_TOPS, "unit": "TFLOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None},
+        "roofline_gather": {"bound": "lds", "achieved": gather, "peak": LDS_PEAK_GBS,
+                            "unit": "GB/s", "frac": gather / LDS_PEAK_GBS},
     }
     if not args.no_check:
         log("per-stack search of every stack (comparison and timing)")
         same = True
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
         plain_ms = 0.0
         for it, res in zip(items, plan.results):
             e0 = torch.cuda.Event(enable_timing=True)
@@ -455,7 +595,8 @@ def bench_batch62(args):
                                    "batched_search_ms": search_ms,
                                    "speedup": plain_ms / search_ms}
     plan.close()
-    print(json.dumps(rec), flush=True)
+    del plan, items, geo
+    return rec
 
 
 def recovered(sources, params, lh, lh_min=10.0, pos_tol=5.0, vel_tol=5.0):
@@ -478,10 +619,8 @@ def bench_pipeline(args):
     sigma 1.6 on 11 x 11, 200 sources with per-epoch SNR in [2, 10]):
     dense 256 x 256 search + extraction of every slot with L' >= 10 (up to
     10^6), against coarse 64 x 64 search + top 10^6 + 50 refinement steps +
-    scoring of the refined trajectories.  Reports recovered-source sets and
-    the time ratio."""
-    import math
-
+    scoring of the refined trajectories.  Returns the record: recovered-
+    source sets and the time ratio."""
     import numpy as np
     import torch
 
@@ -491,7 +630,8 @@ def bench_pipeline(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    size = tuple(int(v) for v in args.size.split("x")) if args.size else None
+    size = tuple(int(v) for v in args.size.split("x")) if (args.size and
+                                                           args.workload == "pipeline") else None
     log("generating the full-pipeline stack")
     st = synth.make_config(5, size=size)
     T, H, W = st.sci.shape
@@ -566,7 +706,8 @@ def bench_pipeline(args):
             "only_coarse_refined": sorted(rec_coarse - rec_dense),
         },
     }
-    print(json.dumps(rec), flush=True)
+    del psi, phi, out
+    return rec
 
 
 def bench_respix(args):

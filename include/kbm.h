@@ -56,6 +56,9 @@ const char *kbm_status_string(kbm_status s);
 const char *kbm_last_error(void);
 /* Library version, major*10000 + minor*100 + patch. */
 int kbm_version(void);
+/* Id of the sources and flags the library was built from (16 hex digits;
+ * comments do not enter it), so a binding can refuse a stale build. */
+const char *kbm_build_id(void);
 
 /* One aligned image stack (one CCD over T epochs). */
 typedef struct {
@@ -224,6 +227,13 @@ kbm_status kbm_batch_run(kbm_batch *b, hipStream_t stream);
  * completed run gave up (stalled != 0: that run's results are not valid).
  * Each wait is bounded, so a run always ends. */
 kbm_status kbm_batch_check(kbm_batch *b, hipStream_t stream, int32_t *stalled);
+
+/* Synchronise `stream` and report how many trajectory-epochs (start pixel x
+ * velocity x epoch) the last completed run evaluated: the nominal
+ * W*H*V*T of every stack minus the (64-pixel row tile, velocity) pairs the
+ * kernel skipped because no start pixel of the tile can keep min_obs epochs
+ * inside the image (their slots are empty either way). */
+kbm_status kbm_batch_evaluated(kbm_batch *b, hipStream_t stream, uint64_t *traj_epochs);
 
 /* Release the plan (graph, stream, host buffers); NULL is a no-op. */
 kbm_status kbm_batch_destroy(kbm_batch *b);

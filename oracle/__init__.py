@@ -70,6 +70,8 @@ def _load():
         lib.kbmo_score.argtypes = [i32, i32, i32, P, P, P, i64, P, i32, i32, f64,
                                    f64, f64, f64, P, P, P, P, P]
         lib.kbmo_num_threads.restype = C.c_int
+        lib.kbmo_set_num_threads.argtypes = [C.c_int]
+        lib.kbmo_set_num_threads.restype = None
         _lib = lib
         return lib
 
@@ -84,6 +86,11 @@ def _c(a, dt):
 
 def num_threads() -> int:
     return int(_load().kbmo_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads the oracle's parallel loops use from now on (OpenMP)."""
+    _load().kbmo_set_num_threads(int(n))
 
 
 def planes(sci, var, mask, psf):

@@ -43,6 +43,15 @@
 
 #define KBMO_MAX_T 64
 
+void kbmo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int kbmo_num_threads(void)
 {
 #ifdef _OPENMP

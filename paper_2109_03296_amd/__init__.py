@@ -29,6 +29,7 @@ __all__ = [
     "MAX_PSF", "extract_top", "adam_step", "refine", "BatchedSearch",
     "Schedule", "batch_workspace_size", "extract_workspace_size",
     "score_trajectories", "stamps", "STAMP_LIMITS", "sigmag_filter_ex", "sigmag_coeff",
+    "Refiner",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -66,17 +67,24 @@ class _Results(C.Structure):
 
 
 def lib():
-    """Load libkbm.so (building it first only if it does not exist)."""
+    """Load libkbm.so (building it first only if it does not exist).  A
+    library built from other sources or flags than the ones in the tree is
+    refused: its build id must equal the id of the current sources."""
     global _lib
     with _lock:
         if _lib is not None:
             return _lib
+        from . import build as _build
         if not os.path.exists(LIB_PATH):
-            from . import build as _build
             _build.build()
         if not os.path.exists(LIB_PATH):
             raise ImportError("libkbm.so is missing and could not be built")
         L = C.CDLL(LIB_PATH)
+        L.kbm_build_id.restype = C.c_char_p
+        built, want = L.kbm_build_id().decode(), _build.source_hash()
+        if built != want:
+            raise ImportError(f"libkbm.so was built from other sources (build id {built}, "
+                              f"sources {want}); rebuild it (__graft_entry__.build())")
         P, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.kbm_status_string.restype = C.c_char_p
         L.kbm_status_string.argtypes = [C.c_int]
@@ -99,6 +107,7 @@ def lib():
                                        P, P, P]
         L.kbm_batch_run.argtypes = [P, P]
         L.kbm_batch_check.argtypes = [P, P, P]
+        L.kbm_batch_evaluated.argtypes = [P, P, P]
         L.kbm_batch_destroy.argtypes = [P]
         L.kbm_score_trajectories.argtypes = [P, P, P, i64, P, i32, i32, f64, f64,
                                              f64, f64, P, P, P, P, P, P]
@@ -422,6 +431,15 @@ class BatchedSearch:
             self._h, _stream(stream), C.byref(stalled)))
         return bool(stalled.value)
 
+    def evaluated(self, stream=None) -> int:
+        """Synchronise and return the trajectory-epochs the last run
+        evaluated (the nominal count minus the tile-velocity pairs skipped
+        because no start pixel of the tile can keep min_obs epochs)."""
+        n = C.c_uint64(0)
+        _check("kbm_batch_evaluated", lib().kbm_batch_evaluated(
+            self._h, _stream(stream), C.byref(n)))
+        return int(n.value)
+
     def close(self):
         if getattr(self, "_h", None):
             lib().kbm_batch_destroy(self._h)
@@ -492,8 +510,9 @@ def sigmag_coeff(q_lo, q_hi) -> float:
     return float(c.value)
 
 
-def refine_forward(psi, phi, times, params, keep=None, stream=None):
-    """Bilinear likelihood L for ``[n][4]`` params (x0, y0, vx, vy)."""
+def refine_forward(psi, phi, times, params, keep=None, stream=None, out=None):
+    """Bilinear likelihood L for ``[n][4]`` params (x0, y0, vx, vy); written
+    into ``out`` (float [n]) when given."""
     _dev(psi, torch.float32, "psi")
     _dev(phi, torch.float32, "phi", psi.shape)
     _dev(params, torch.float32, "params")
@@ -502,7 +521,10 @@ def refine_forward(psi, phi, times, params, keep=None, stream=None):
     if keep is not None:
         _dev(keep, torch.int64, "keep", (n,))
     st, _t = _stack(T, H, W, times)
-    lh = torch.empty(n, dtype=torch.float32, device=psi.device)
+    if out is None:
+        lh = torch.empty(n, dtype=torch.float32, device=psi.device)
+    else:
+        lh = _dev(out, torch.float32, "out", (n,))
     _check("kbm_refine", lib().kbm_refine(
         C.byref(st), _ptr(psi), _ptr(phi), n, _ptr(params), _ptr(keep),
         _ptr(lh), None, None, None, None, _stream(stream)))
@@ -510,9 +532,10 @@ def refine_forward(psi, phi, times, params, keep=None, stream=None):
 
 
 def refine_backward(psi, phi, times, params, grad_lh, keep=None,
-                    grad_psi=None, grad_phi=None, stream=None):
+                    grad_psi=None, grad_phi=None, stream=None, out=None):
     """(lh, g * dL/dparams); g * dL/dpsi, g * dL/dphi are added into
-    grad_psi / grad_phi when given."""
+    grad_psi / grad_phi when given.  ``out = (lh, grad_params)`` receives
+    the two results when given (float [n] and [n][4])."""
     _dev(psi, torch.float32, "psi")
     _dev(phi, torch.float32, "phi", psi.shape)
     _dev(params, torch.float32, "params")
@@ -525,8 +548,12 @@ def refine_backward(psi, phi, times, params, grad_lh, keep=None,
         if g is not None:
             _dev(g, torch.float32, nm, psi.shape)
     st, _t = _stack(T, H, W, times)
-    lh = torch.empty(n, dtype=torch.float32, device=psi.device)
-    gp = torch.empty((n, 4), dtype=torch.float32, device=psi.device)
+    if out is None:
+        lh = torch.empty(n, dtype=torch.float32, device=psi.device)
+        gp = torch.empty((n, 4), dtype=torch.float32, device=psi.device)
+    else:
+        lh = _dev(out[0], torch.float32, "out lh", (n,))
+        gp = _dev(out[1], torch.float32, "out grad", (n, 4))
     _check("kbm_refine", lib().kbm_refine(
         C.byref(st), _ptr(psi), _ptr(phi), n, _ptr(params), _ptr(keep),
         _ptr(lh), _ptr(grad_lh), _ptr(gp), _ptr(grad_psi), _ptr(grad_phi),
@@ -679,25 +706,131 @@ def adam_step(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8,
         int(bool(maximize)), _stream(stream)))
 
 
+def _refine_lrs(times, steps, lr_pos, lr_vel, cosine):
+    """Per-step Adam step sizes [steps][4] of the refinement loop."""
+    t = np.asarray(times, np.float64)
+    span = float(t.max() - t.min()) or 1.0
+    lr_vel = lr_pos / span if lr_vel is None else lr_vel
+    out = []
+    for it in range(1, steps + 1):
+        scale = 0.5 * (1.0 + np.cos(np.pi * (it - 1) / steps)) if cosine else 1.0
+        out.append([lr_pos * scale, lr_pos * scale, lr_vel * scale, lr_vel * scale])
+    return out
+
+
+def _refine_steps(psi, phi, times, p, m, v, g, lh, ones, keep, lrs, stream):
+    """The refinement loop on fixed buffers: moments cleared by a kernel,
+    then per step the adjoint kernel and one Adam kernel, then L at the
+    final parameters.  Only kernel launches (capturable)."""
+    m.zero_()
+    v.zero_()
+    for it, lr in enumerate(lrs, start=1):
+        refine_backward(psi, phi, times, p, ones, keep, stream=stream, out=(lh, g))
+        adam_step(p, g, m, v, lr, it, maximize=True, stream=stream)
+    refine_forward(psi, phi, times, p, keep, stream=stream, out=lh)
+
+
 def refine(psi, phi, times, params0, keep=None, steps=50, lr_pos=0.3,
-           lr_vel=None, cosine=True, stream=None):
+           lr_vel=None, cosine=True, stream=None, graph=True):
     """Gradient-ascent refinement of candidates with the bilinear adjoint.
 
     Each step runs the adjoint kernel (L and dL/dparams) and one Adam update
     kernel.  Position steps are ``lr_pos`` pixels; velocity steps default to
     ``lr_pos / t_span`` px/day so that both move the track by similar
-    amounts.  A cosine decay scales both.  Returns (params, lh) where lh is
-    the likelihood at the returned params."""
-    t = np.asarray(times, np.float64)
-    span = float(t.max() - t.min()) or 1.0
-    lr_vel = lr_pos / span if lr_vel is None else lr_vel
+    amounts.  A cosine decay scales both.  With ``graph`` the loop is
+    replayed from a HIP graph captured once per problem (see Refiner);
+    otherwise its kernels are launched one by one.  Both run the same
+    kernels with the same arguments in the same order.  Returns (params, lh)
+    where lh is the likelihood at the returned params."""
+    if graph:
+        r = _refiner_for(psi, phi, times, params0.shape[0], keep is not None, steps,
+                         lr_pos, lr_vel, cosine)
+        p, lh = r.run(params0.contiguous(), keep, stream=stream)
+        return p.clone(), lh.clone()
     p = params0.detach().clone().contiguous()
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
+    g = torch.empty_like(p)
+    lh = torch.empty(p.shape[0], dtype=torch.float32, device=p.device)
     ones = torch.ones(p.shape[0], dtype=torch.float32, device=p.device)
-    for it in range(1, steps + 1):
-        scale = 0.5 * (1.0 + np.cos(np.pi * (it - 1) / steps)) if cosine else 1.0
-        _, g = refine_backward(psi, phi, times, p, ones, keep, stream=stream)
-        adam_step(p, g, m, v, [lr_pos * scale, lr_pos * scale, lr_vel * scale,
-                               lr_vel * scale], it, maximize=True, stream=stream)
-    return p, refine_forward(psi, phi, times, p, keep, stream=stream)
+    _refine_steps(psi, phi, times, p, m, v, g, lh, ones, keep,
+                  _refine_lrs(times, steps, lr_pos, lr_vel, cosine), stream)
+    return p, lh
+
+
+class Refiner:
+    """The refinement loop of ``refine`` for ``n`` candidates on fixed planes,
+    captured once into a HIP graph (every step's adjoint and Adam kernels,
+    the cosine step sizes baked in) and replayed per call: one graph launch
+    instead of 2 * steps + 3 kernel launches from Python.
+
+    ``run(params0, keep)`` copies the starting parameters (and keep masks, if
+    the refiner was made ``with_keep``) into the graph's buffers, replays it
+    on the current (or given) stream and returns its (params, lh) buffers,
+    valid until the next run.  The planes must stay allocated while the
+    refiner lives (their addresses are baked into the graph)."""
+
+    def __init__(self, psi, phi, times, n, with_keep=False, steps=50, lr_pos=0.3,
+                 lr_vel=None, cosine=True):
+        _dev(psi, torch.float32, "psi")
+        _dev(phi, torch.float32, "phi", psi.shape)
+        dev = psi.device
+        self.n, self.with_keep = int(n), bool(with_keep)
+        self.psi, self.phi, self.times = psi, phi, np.asarray(times, np.float64).copy()
+        self.p = torch.zeros((self.n, 4), dtype=torch.float32, device=dev)
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.g = torch.zeros_like(self.p)
+        self.lh = torch.zeros(self.n, dtype=torch.float32, device=dev)
+        self.ones = torch.ones(self.n, dtype=torch.float32, device=dev)
+        self.keep = torch.zeros(self.n, dtype=torch.int64, device=dev) if with_keep else None
+        self.lrs = _refine_lrs(times, steps, lr_pos, lr_vel, cosine)
+        self.graph = None
+        if self.n == 0:
+            return
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            # one eager pass loads the kernels' code objects before capture
+            self._steps()
+        torch.cuda.current_stream(dev).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._steps()
+
+    def _steps(self):
+        _refine_steps(self.psi, self.phi, self.times, self.p, self.m, self.v, self.g,
+                      self.lh, self.ones, self.keep, self.lrs, None)
+
+    def run(self, params0, keep=None, stream=None):
+        _dev(params0, torch.float32, "params0", (self.n, 4))
+        if (keep is not None) != self.with_keep:
+            raise ValueError("keep must be given exactly when the refiner was made with_keep")
+        if self.n == 0:
+            return self.p, self.lh
+        s = torch.cuda.current_stream() if stream is None else stream
+        with torch.cuda.stream(s):
+            self.p.copy_(params0)
+            if keep is not None:
+                self.keep.copy_(_dev(keep, torch.int64, "keep", (self.n,)))
+            self.graph.replay()
+        return self.p, self.lh
+
+
+_refiners = {}
+
+
+def _refiner_for(psi, phi, times, n, with_keep, steps, lr_pos, lr_vel, cosine):
+    """A Refiner for this problem, reused while the planes, times, size and
+    step sizes stay the same (the four most recent are kept)."""
+    key = (psi.data_ptr(), phi.data_ptr(), tuple(psi.shape), psi.device.index,
+           tuple(np.asarray(times, np.float64).tolist()), int(n), bool(with_keep),
+           int(steps), float(lr_pos), None if lr_vel is None else float(lr_vel),
+           bool(cosine))
+    r = _refiners.pop(key, None)
+    if r is None:
+        r = Refiner(psi, phi, times, n, with_keep, steps, lr_pos, lr_vel, cosine)
+        while len(_refiners) >= 4:
+            _refiners.pop(next(iter(_refiners)))
+    _refiners[key] = r
+    return r

@@ -8,7 +8,9 @@ and packed-FP32 instruction selection disabled.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
+import re
 import subprocess
 import sys
 
@@ -25,7 +27,7 @@ SOURCES = ["api.cpp", "planes.hip", "search.hip", "search_exact_a.hip",
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-FLAGS = [
+FLAGS_BASE = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -34,10 +36,41 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, extra=(), build_dir=None) -> str:
+_COMMENT_OR_LITERAL = re.compile(
+    r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'', re.S)
+
+
+def _strip_comments(text: str) -> str:
+    """C/C++ source without comments (string and character literals kept,
+    so a '//' inside a literal is not taken for a comment) and without
+    blank lines or trailing spaces."""
+    def keep(m):
+        t = m.group(0)
+        return t if t[0] in "\"'" else (" " if t.startswith("/*") else "")
+    code = _COMMENT_OR_LITERAL.sub(keep, text)
+    return "\n".join(l.rstrip() for l in code.splitlines() if l.strip())
+
+
+def source_hash(extra=()) -> str:
+    """Build id of the current sources: every file under csrc/ and the
+    public header with comments removed, plus the compile flags (include
+    paths aside, which depend on where the tree sits) and any extra flags.
+    A comment edit keeps the id; any code or flag change alters it."""
+    h = hashlib.sha256()
+    files = sorted(os.listdir(CSRC))
+    for f in files:
+        with open(os.path.join(CSRC, f), encoding="utf-8") as fh:
+            h.update(f.encode() + b"\0" + _strip_comments(fh.read()).encode() + b"\0")
+    with open(os.path.join(INCLUDE, "kbm.h"), encoding="utf-8") as fh:
+        h.update(b"kbm.h\0" + _strip_comments(fh.read()).encode() + b"\0")
+    h.update(" ".join(f for f in [*FLAGS_BASE, *extra] if not f.startswith("-I")).encode())
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, extra=(), build_dir=None, build_id="unknown") -> str:
     obj = os.path.join(build_dir or BUILD_DIR, src + ".o")
-    cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src),
-           "-o", obj]
+    cmd = [HIPCC, *FLAGS_BASE, f'-DKBM_BUILD_ID="{build_id}"', *extra, "-x", "hip",
+           "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")
@@ -55,7 +88,8 @@ def build(extra_flags=(), jobs: int = 8, lib=None, build_dir=None) -> str:
     build_dir = build_dir or BUILD_DIR
     os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra_flags, build_dir), SOURCES))
+        bid = source_hash(extra_flags)
+        objs = list(ex.map(lambda s: _compile(s, extra_flags, build_dir, bid), SOURCES))
     tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)

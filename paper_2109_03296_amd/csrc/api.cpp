@@ -164,4 +164,9 @@ const char *kbm_last_error(void) { return kbm::g_last_error.c_str(); }
 
 int kbm_version(void) { return 100; }  // 0.1.0
 
+#ifndef KBM_BUILD_ID
+#define KBM_BUILD_ID "unknown"
+#endif
+const char *kbm_build_id(void) { return KBM_BUILD_ID; }
+
 }  // extern "C"

@@ -532,6 +532,7 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
         a.coeff = (float)q.coeff;
         a.n_sigma = (float)q.n_sigma;
         a.defq = q.q_lo == 0.25 && q.q_hi == 0.75;
+        a.evals = reinterpret_cast<unsigned long long *>(b->ctrl + CTRL_EVALS);
         b->T.push_back(a.T);
         b->V.push_back(a.V);
         b->Wr.push_back(a.Wr);
@@ -614,6 +615,21 @@ extern "C" kbm_status kbm_batch_check(kbm_batch *b, hipStream_t stream, int32_t 
                            hipMemcpyDeviceToHost, stream));
     KBM_HIP(hipStreamSynchronize(stream));
     *stalled = b->host_word[0] != 0u;
+    return KBM_OK;
+}
+
+extern "C" kbm_status kbm_batch_evaluated(kbm_batch *b, hipStream_t stream,
+                                          uint64_t *traj_epochs) {
+    using namespace kbm;
+    clear_error();
+    KBM_REQUIRE(b != nullptr && traj_epochs != nullptr, KBM_ERR_INVALID_ARG,
+                "kbm_batch_evaluated: batch and traj_epochs must be non-NULL");
+    KBM_HIP(hipMemcpyAsync(b->host_word, b->ctrl + batch::CTRL_EVALS, sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, stream));
+    KBM_HIP(hipStreamSynchronize(stream));
+    uint64_t v = 0;
+    std::memcpy(&v, b->host_word, sizeof(v));
+    *traj_epochs = v;
     return KBM_OK;
 }
 

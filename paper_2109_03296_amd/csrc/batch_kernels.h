@@ -19,7 +19,9 @@ constexpr int MAX_T = 32;         // exact epoch counts compiled in
 constexpr int PAD_COLS = 16;      // every allowed tile_cols divides this
 constexpr int PAD_ROWS = 64;      // every allowed tile_rows divides this
 constexpr int MIN_VB = 32;
-constexpr int CTRL_HEAD = 64;     // words: queue heads [0, 8), stall flag [8]
+constexpr int CTRL_HEAD = 64;     // words: queue heads [0, 8), stall flag [8],
+                                  // evaluated trajectory-epochs (u64) [16, 18)
+constexpr int CTRL_EVALS = 16;
 constexpr uint32_t SPIN_LIMIT = 1u << 20;  // polls before a wait gives up
 
 struct PrepDesc {

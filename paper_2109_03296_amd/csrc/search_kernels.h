@@ -117,6 +117,8 @@ struct SearchArgs {
     int v_begin, v_end, first;
     float coeff, n_sigma;
     int defq;                 // quantiles are (0.25, 0.75): fixed ranks
+    unsigned long long *evals;  // or NULL: adds the trajectory-epochs evaluated
+                                // (those not skipped as unable to reach min_obs)
 };
 
 __device__ __forceinline__ bool ranks_before(float la, int ia, float lb,
@@ -489,6 +491,7 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     const int v_last = CONTIG ? min(v_end, v_first + span) : v_end;
     constexpr int v_step = CONTIG ? 1 : NWT;
     constexpr int same_at = (CONTIG || NWT == 1) ? 4 : 5;
+    int n_eval = 0;  // velocities this wave evaluated (not skipped)
     for (int v = v_first; v < v_last; v += v_step) {
         // The velocity's box (and for T <= 32 its offset row) is read up
         // front, as one batch of scalar loads with one wait, and the box
@@ -509,6 +512,7 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
                 continue;
             }
         }
+        ++n_eval;
         float nu[TM], s[TM];
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
@@ -565,6 +569,9 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
             kI[0] = c0 ? v : kI[0];
         }
     }
+    if (a.evals != nullptr && lane == 0 && n_eval > 0)
+        atomicAdd(a.evals, (unsigned long long)n_eval *
+                               (unsigned long long)(min(WAVE, a.Wr - tx * WAVE) * T));
     if (NWT > 1) {
         // Merge the waves' lists into wave 0's through LDS.  The ranking
         // compares velocity indices on ties, so the merge order is immaterial.

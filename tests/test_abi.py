@@ -37,6 +37,29 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, n), n
 
 
+def test_build_id_matches_sources(L):
+    from paper_2109_03296_amd import build
+    L.kbm_build_id.restype = C.c_char_p
+    assert L.kbm_build_id().decode() == build.source_hash()
+
+
+def test_source_hash_ignores_comments_only(tmp_path, monkeypatch):
+    """A comment edit keeps the build id; code (even a '//' inside a string
+    literal) and extra flags change it."""
+    import shutil
+    from paper_2109_03296_amd import build
+    src = tmp_path / "csrc"
+    shutil.copytree(build.CSRC, src)
+    monkeypatch.setattr(build, "CSRC", str(src))
+    h0 = build.source_hash()
+    f = src / "sigmag.hip"
+    f.write_text(f.read_text() + "\n// a new comment\n/* and\n another */\n")
+    assert build.source_hash() == h0
+    f.write_text(f.read_text() + 'static const char *s = "// not a comment";\n')
+    assert build.source_hash() != h0
+    assert build.source_hash(("-DX=1",)) != build.source_hash()
+
+
 def test_status_strings(L):
     assert L.kbm_status_string(0) == b"ok"
     assert L.kbm_status_string(1) == b"invalid argument"

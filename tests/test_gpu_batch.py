@@ -217,3 +217,46 @@ def test_search_batched_default_is_persistent(kbm, batch):
     torch.cuda.synchronize()
     for b, r in zip(batch, res):
         _equal(r, b["plain"])
+
+
+def _valid_count(times, vels, W, H, min_obs):
+    """Grid trajectories with at least min_obs epochs inside the image
+    (brute force over every start pixel)."""
+    t = np.asarray(times, np.float64)
+    t = t - t.min()
+    v = np.asarray(vels, np.float32).astype(np.float64)
+    ys, xs = np.mgrid[0:H, 0:W]
+    n = 0
+    for j in range(v.shape[0]):
+        c = np.zeros((H, W), np.int64)
+        for ti in t:
+            dx, dy = np.floor(v[j, 0] * ti + 0.5), np.floor(v[j, 1] * ti + 0.5)
+            c += (xs + dx >= 0) & (xs + dx < W) & (ys + dy >= 0) & (ys + dy < H)
+        n += int(np.sum(c >= min_obs))
+    return n
+
+
+def test_batch_evaluated_count(kbm):
+    """The evaluated trajectory-epoch count: every trajectory when no track
+    can leave the image far enough to fall below min_obs; otherwise at most
+    the nominal count and at least T x the valid trajectories (a skipped
+    (tile, velocity) pair holds no valid trajectory)."""
+    rng = np.random.default_rng(5)
+    T, H, W = 9, 40, 150
+    times = np.sort(rng.uniform(0, 2, T))
+    psi = torch.from_numpy(rng.normal(size=(T, H, W)).astype(np.float32)).cuda()
+    phi = torch.ones_like(psi)
+    slow = rng.uniform(-3, 3, size=(40, 2)).astype(np.float32)
+    fast = np.concatenate([slow, rng.uniform(-60, 60, size=(80, 2)).astype(np.float32)])
+    for vels, min_obs, exact in ((slow, 1, True), (fast, 6, False)):
+        item = dict(psi=psi, phi=phi, times=times, vels=vels,
+                    params=kbm.SearchParams(k=3, min_obs=min_obs))
+        with kbm.BatchedSearch([item, item]) as plan:
+            plan.run()
+            assert not plan.check()
+            n = plan.evaluated()
+        nominal = 2 * T * H * W * len(vels)
+        if exact:
+            assert n == nominal
+        else:
+            assert 2 * T * _valid_count(times, vels, W, H, min_obs) <= n < nominal

@@ -358,6 +358,59 @@ def test_refine_fd_fp32_and_autograd(kbm, oracle_mod):
     assert np.median(rel) < 1e-2
 
 
+def test_trajlh_plane_gradients_through_autograd(kbm, oracle_mod):
+    """TrajLH with psi and phi requiring grad: autograd returns the adjoint's
+    parameter gradient and its scatter-added plane gradients, both against
+    the FP64 oracle (upstream gradient of a weighted sum, keep masks given)."""
+    st, psi, phi, params, keep = _refine_setup(oracle_mod, n=400, seed=12)
+    w = np.random.default_rng(13).normal(size=len(params))
+    P_ = _cuda(params).requires_grad_(True)
+    psi_t = _cuda(psi).requires_grad_(True)
+    phi_t = _cuda(phi).requires_grad_(True)
+    L = kbm.TrajLH.apply(P_, psi_t, phi_t, st.times, _cuda(keep.view(np.int64)))
+    (L * _cuda(w.astype(np.float32))).sum().backward()
+    rl, rg, rpsi, rphi = oracle_mod.refine(psi, phi, st.times, params, keep,
+                                           grad_lh=w.astype(np.float32).astype(np.float64),
+                                           want_planes=True)
+    assert np.all(P.lh_close(L.detach().cpu().numpy(), rl))
+    g = P_.grad.cpu().numpy().astype(np.float64)
+    den = np.linalg.norm(rg, axis=1)
+    big = den > 1e-3 * np.median(den[den > 0])
+    assert np.all(np.linalg.norm(g - rg, axis=1)[big] <= 1e-4 * den[big] + 1e-6)
+    for got, want in ((psi_t.grad, rpsi), (phi_t.grad, rphi)):
+        scale = np.abs(want).max()
+        assert scale > 0
+        assert np.allclose(got.cpu().numpy(), want, rtol=1e-4, atol=1e-5 * scale)
+
+
+def test_refine_graph_matches_eager(kbm, oracle_mod):
+    """The refinement loop replayed from its captured graph gives bit for bit
+    what the eager launches give, on several replays with other inputs and
+    eager work between them, with and without keep masks."""
+    st, psi, phi, params, keep = _refine_setup(oracle_mod, n=700, seed=14)
+    gpsi, gphi = _cuda(psi), _cuda(phi)
+    rng = np.random.default_rng(15)
+    r = kbm.Refiner(gpsi, gphi, st.times, len(params), with_keep=True, steps=20)
+    r0 = kbm.Refiner(gpsi, gphi, st.times, len(params), steps=20)
+    for rep in range(3):
+        p0 = params + rng.normal(scale=0.3, size=params.shape).astype(np.float32)
+        k0 = _cuda(keep.view(np.int64))
+        pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(p0), k0, steps=20, graph=False)
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        pg, lg = r.run(_cuda(p0), k0)
+        torch.cuda.synchronize()
+        assert torch.equal(pg, pe) and torch.equal(lg, le), rep
+        pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(p0), None, steps=20, graph=False)
+        pg, lg = r0.run(_cuda(p0))
+        torch.cuda.synchronize()
+        assert torch.equal(pg, pe) and torch.equal(lg, le), rep
+        del junk
+    # refine() itself goes through a cached graph by default
+    pd, ld = kbm.refine(gpsi, gphi, st.times, _cuda(params), None, steps=20)
+    pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(params), None, steps=20, graph=False)
+    assert torch.equal(pd, pe) and torch.equal(ld, le)
+
+
 @pytest.mark.parametrize("quantity,ql,qh", [(1, 0.25, 0.75), (0, 0.1, 0.9), (1, 0.16, 0.84)])
 def test_sigmag_filter_variants(kbm, oracle_mod, quantity, ql, qh):
     """Flux quantity, other quantile pairs with C of Eq. 3, and the ΣLH'
