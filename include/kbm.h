@@ -401,6 +401,32 @@ kbm_status kbm_extract_top(const kbm_results *r, int32_t Hr, int32_t Wr,
                            size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * kbm_extract_top_noalloc - kbm_extract_top for callers that cannot
+ * allocate device or pinned host memory: code under HIP graph capture,
+ * tight serving loops, hosts that forbid allocation.  It calls no
+ * hipMalloc, hipFree or hipHostMalloc and copies nothing from the host.
+ *
+ * Same selection, order, outputs and limits as kbm_extract_top, except:
+ *   vel_dev : DEVICE float [num_vel][2], the velocity list the search used
+ *   (no workspace argument)
+ * Scratch: the radix-select state and per-block counts live in a static
+ * device array of the library, KBM_EXTRACT_SCRATCH_BYTES per GPU, held
+ * until the process ends; every call needs at most that much, whatever the
+ * number of slots (below 2^32).  All calls on one GPU share it and it keeps
+ * the last call's contents (each call re-initialises what it reads): calls
+ * that overlap on one GPU race and must be serialised by the caller, e.g.
+ * on one stream.
+ */
+#define KBM_EXTRACT_SCRATCH_BYTES 17664
+kbm_status kbm_extract_top_noalloc(const kbm_results *r, int32_t Hr, int32_t Wr,
+                                   int32_t k, int32_t x_begin, int32_t y_begin,
+                                   const float *vel_dev, int32_t num_vel,
+                                   float lh_min, int64_t n_max, float *params,
+                                   float *lh, float *flux, uint64_t *keep,
+                                   int64_t *index, int16_t *n_obs, int64_t *n_out,
+                                   hipStream_t stream);
+
+/*
  * kbm_adam_step - one Adam update (Kingma & Ba 2015, Algorithm 1) of the
  * refinement parameters, the optimiser that drives kbm_refine's gradient
  * ascent.  With g the gradient (negated when maximize != 0):

@@ -29,7 +29,7 @@ __all__ = [
     "MAX_PSF", "extract_top", "adam_step", "refine", "BatchedSearch",
     "Schedule", "batch_workspace_size", "extract_workspace_size",
     "score_trajectories", "stamps", "STAMP_LIMITS", "sigmag_filter_ex", "sigmag_coeff",
-    "Refiner",
+    "extract_top_noalloc", "Refiner",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -100,6 +100,8 @@ def lib():
         L.kbm_extract_top.argtypes = [P, i32, i32, i32, i32, i32, P, i32,
                                       C.c_float, i64, P, P, P, P, P, P, P, P,
                                       C.c_size_t, P]
+        L.kbm_extract_top_noalloc.argtypes = [P, i32, i32, i32, i32, i32, P, i32,
+                                              C.c_float, i64, P, P, P, P, P, P, P, P]
         L.kbm_adam_step.argtypes = [P, P, P, P, i64, i32, P, f64, f64, f64,
                                     i32, i32, P]
         L.kbm_batch_workspace_size.argtypes = [P, P, i32, P]
@@ -691,6 +693,45 @@ def extract_top(res, vels, n_max, lh_min=-float("inf"), region_origin=(0, 0),
         workspace.numel(), _stream(stream)))
     n = int(n_out.item())
     return {key: v[:n] for key, v in out.items()}
+
+
+def extract_top_noalloc(res, vels, n_max, out, n_out, lh_min=-float("inf"),
+                        region_origin=(0, 0), stream=None):
+    """extract_top for callers that cannot allocate: nothing is allocated here
+    or in the library (its scratch is a static device array per GPU, so
+    overlapping calls on one GPU race).  ``vels`` is a device float tensor
+    [V][2]; ``out`` holds caller-allocated device tensors params [>=n_max][4],
+    lh, flux, keep (int64), index (int64), n_obs (int16) of >= n_max rows
+    (flux, keep, index, n_obs may be None); ``n_out`` a device int64 [1] that
+    receives the number written.  Returns ``n_out``."""
+    lh_t = _dev(res["lh"], torch.float32, "lh")
+    Hr, Wr, k = lh_t.shape
+    _dev(vels, torch.float32, "vels")
+    if vels.dim() != 2 or vels.shape[1] != 2:
+        raise ValueError("vels must be a device float tensor [V][2]")
+    n_max = int(n_max)
+    for key, dt in (("params", torch.float32), ("lh", torch.float32),
+                    ("flux", torch.float32), ("keep", torch.int64),
+                    ("index", torch.int64), ("n_obs", torch.int16)):
+        t = out.get(key)
+        if t is None:
+            if key in ("params", "lh"):
+                raise ValueError(f"out[{key!r}] is required")
+            continue
+        _dev(t, dt, key)
+        if t.shape[0] < n_max:
+            raise ValueError(f"out[{key!r}] holds {t.shape[0]} rows, n_max is {n_max}")
+    _dev(n_out, torch.int64, "n_out")
+    r = _Results(res["lh"].data_ptr(), res["flux"].data_ptr(),
+                 res["vel_idx"].data_ptr(), res["n_obs"].data_ptr(),
+                 res["keep"].data_ptr(), None)
+    _check("kbm_extract_top_noalloc", lib().kbm_extract_top_noalloc(
+        C.byref(r), Hr, Wr, k, int(region_origin[0]), int(region_origin[1]),
+        _ptr(vels), vels.shape[0], float(lh_min), n_max,
+        _ptr(out["params"]), _ptr(out["lh"]), _ptr(out.get("flux")),
+        _ptr(out.get("keep")), _ptr(out.get("index")), _ptr(out.get("n_obs")),
+        _ptr(n_out), _stream(stream)))
+    return n_out
 
 
 def adam_step(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8,

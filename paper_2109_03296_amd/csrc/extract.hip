@@ -11,6 +11,8 @@
 // compaction (block counts, one scan, block-local ballot ranks) then writes
 // the selected slots in flat-index order.  Slots below the threshold, empty
 // or non-finite never take part.
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "kbm_internal.h"
@@ -252,41 +254,42 @@ extern "C" kbm_status kbm_extract_workspace_size(int32_t Hr, int32_t Wr, int32_t
     return KBM_OK;
 }
 
-extern "C" kbm_status kbm_extract_top(const kbm_results *r, int32_t Hr, int32_t Wr,
-                                      int32_t k, int32_t x_begin, int32_t y_begin,
-                                      const float *vel, int32_t num_vel, float lh_min,
-                                      int64_t n_max, float *params, float *lh,
-                                      float *flux, uint64_t *keep, int64_t *index,
-                                      int16_t *n_obs, int64_t *n_out,
-                                      void *workspace, size_t workspace_bytes,
-                                      hipStream_t stream) {
-    using namespace kbm;
-    clear_error();
+namespace kbm {
+namespace {
+
+// Validation shared by both entry points; returns the slot count in *n.
+kbm_status check_extract(const char *who, const kbm_results *r, int32_t Hr, int32_t Wr,
+                         int32_t k, const float *vel, int32_t num_vel, float lh_min,
+                         int64_t n_max, const float *params, const float *lh,
+                         const float *flux, const uint64_t *keep, const int16_t *n_obs,
+                         const int64_t *n_out, uint64_t *n) {
     KBM_REQUIRE(r != nullptr && r->lh && r->vel_idx, KBM_ERR_INVALID_ARG,
-                "kbm_extract_top: results (lh, vel_idx) must be non-NULL");
+                "%s: results (lh, vel_idx) must be non-NULL", who);
     KBM_REQUIRE(Hr >= 0 && Wr >= 0 && k >= 1 && k <= KBM_MAX_K, KBM_ERR_INVALID_ARG,
-                "kbm_extract_top: bad result shape %d x %d x %d", Hr, Wr, k);
+                "%s: bad result shape %d x %d x %d", who, Hr, Wr, k);
     KBM_REQUIRE(vel != nullptr && num_vel >= 1, KBM_ERR_INVALID_ARG,
-                "kbm_extract_top: velocity list is empty");
+                "%s: velocity list is empty", who);
     KBM_REQUIRE(n_max >= 0 && params && lh && n_out, KBM_ERR_INVALID_ARG,
-                "kbm_extract_top: params, lh and n_out must be non-NULL, n_max >= 0");
-    KBM_REQUIRE(!std::isnan(lh_min), KBM_ERR_INVALID_ARG, "kbm_extract_top: lh_min is NaN");
-    const uint64_t n = (uint64_t)Hr * Wr * k;
-    KBM_REQUIRE(n < ((uint64_t)1 << 32), KBM_ERR_UNSUPPORTED,
-                "kbm_extract_top: more than 2^32 result slots");
-    KBM_REQUIRE(!flux || r->flux, KBM_ERR_INVALID_ARG, "kbm_extract_top: results lack flux");
-    KBM_REQUIRE(!keep || r->keep, KBM_ERR_INVALID_ARG, "kbm_extract_top: results lack keep");
-    KBM_REQUIRE(!n_obs || r->n_obs, KBM_ERR_INVALID_ARG, "kbm_extract_top: results lack n_obs");
-    const ExLayout l = ex_layout(n, num_vel);
-    KBM_REQUIRE(workspace != nullptr && workspace_bytes >= l.end, KBM_ERR_WORKSPACE,
-                "kbm_extract_top: workspace of %zu bytes given, %zu needed",
-                workspace_bytes, l.end);
-    char *ws = static_cast<char *>(workspace);
-    ExtractState *st = reinterpret_cast<ExtractState *>(ws + l.st_off);
-    unsigned int *cnt = reinterpret_cast<unsigned int *>(ws + l.cnt_off);
-    float *dvel = reinterpret_cast<float *>(ws + l.vel_off);
-    kbm_status s = stage_to_device(dvel, vel, sizeof(float) * 2 * (size_t)num_vel, stream);
-    if (s != KBM_OK) return s;
+                "%s: params, lh and n_out must be non-NULL, n_max >= 0", who);
+    KBM_REQUIRE(!std::isnan(lh_min), KBM_ERR_INVALID_ARG, "%s: lh_min is NaN", who);
+    *n = (uint64_t)Hr * Wr * k;
+    KBM_REQUIRE(*n < ((uint64_t)1 << 32), KBM_ERR_UNSUPPORTED,
+                "%s: more than 2^32 result slots", who);
+    KBM_REQUIRE(!flux || r->flux, KBM_ERR_INVALID_ARG, "%s: results lack flux", who);
+    KBM_REQUIRE(!keep || r->keep, KBM_ERR_INVALID_ARG, "%s: results lack keep", who);
+    KBM_REQUIRE(!n_obs || r->n_obs, KBM_ERR_INVALID_ARG, "%s: results lack n_obs", who);
+    return KBM_OK;
+}
+
+// Radix select, block counts, scan and ordered write; `st` and `cnt` are
+// scratch (every word the kernels read is written first by an earlier
+// kernel of the sequence), `dvel` the device velocity list.
+kbm_status enqueue_extract(const kbm_results *r, uint64_t n, const ExLayout &l,
+                           ExtractState *st, unsigned int *cnt, const float *dvel,
+                           int32_t Wr, int32_t k, int32_t x_begin, int32_t y_begin,
+                           float lh_min, int64_t n_max, float *params, float *lh,
+                           float *flux, uint64_t *keep, int64_t *index, int16_t *n_obs,
+                           int64_t *n_out, hipStream_t stream) {
     hipLaunchKernelGGL(ex_init_kernel, dim3(1), dim3(256), 0, stream, st, (uint64_t)n_max);
     for (int pass = 0; pass < 8; ++pass) {
         hipLaunchKernelGGL(ex_hist_kernel, dim3(l.nb), dim3(EX_THREADS), 0, stream,
@@ -317,4 +320,96 @@ extern "C" kbm_status kbm_extract_top(const kbm_results *r, int32_t Hr, int32_t 
                        lh_min, l.per_block, st, cnt);
     KBM_LAUNCHED("ex_write_kernel");
     return KBM_OK;
+}
+
+// Scratch of kbm_extract_top_noalloc: the select state and the per-block
+// counts (at most EX_BLOCKS_MAX blocks whatever the slot count).  Each GPU
+// holds its own copy until the process ends.
+constexpr size_t EX_SCRATCH_BYTES = KBM_EXTRACT_SCRATCH_BYTES;
+static_assert(EX_SCRATCH_BYTES >= (sizeof(ExtractState) + 255) / 256 * 256 +
+                                      sizeof(unsigned int) * EX_BLOCKS_MAX,
+              "scratch of kbm_extract_top_noalloc too small for EX_BLOCKS_MAX blocks");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[EX_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+std::map<int, char *> g_scratch;  // device -> device address of `scratch`
+
+// Device address of this device's scratch, looked up once per device with
+// that device current.
+kbm_status scratch_address(char **out) {
+    int dev = 0;
+    KBM_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void *p = nullptr;
+        KBM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        KBM_REQUIRE(p != nullptr, KBM_ERR_DEVICE,
+                    "kbm_extract_top_noalloc: no device address for the scratch array");
+        it = g_scratch.emplace(dev, static_cast<char *>(p)).first;
+    }
+    *out = it->second;
+    return KBM_OK;
+}
+
+}  // namespace
+}  // namespace kbm
+
+extern "C" kbm_status kbm_extract_top(const kbm_results *r, int32_t Hr, int32_t Wr,
+                                      int32_t k, int32_t x_begin, int32_t y_begin,
+                                      const float *vel, int32_t num_vel, float lh_min,
+                                      int64_t n_max, float *params, float *lh,
+                                      float *flux, uint64_t *keep, int64_t *index,
+                                      int16_t *n_obs, int64_t *n_out,
+                                      void *workspace, size_t workspace_bytes,
+                                      hipStream_t stream) {
+    using namespace kbm;
+    clear_error();
+    uint64_t n = 0;
+    kbm_status s = check_extract("kbm_extract_top", r, Hr, Wr, k, vel, num_vel, lh_min,
+                                 n_max, params, lh, flux, keep, n_obs, n_out, &n);
+    if (s != KBM_OK) return s;
+    const ExLayout l = ex_layout(n, num_vel);
+    KBM_REQUIRE(workspace != nullptr && workspace_bytes >= l.end, KBM_ERR_WORKSPACE,
+                "kbm_extract_top: workspace of %zu bytes given, %zu needed",
+                workspace_bytes, l.end);
+    char *ws = static_cast<char *>(workspace);
+    ExtractState *st = reinterpret_cast<ExtractState *>(ws + l.st_off);
+    unsigned int *cnt = reinterpret_cast<unsigned int *>(ws + l.cnt_off);
+    float *dvel = reinterpret_cast<float *>(ws + l.vel_off);
+    s = stage_to_device(dvel, vel, sizeof(float) * 2 * (size_t)num_vel, stream);
+    if (s != KBM_OK) return s;
+    return enqueue_extract(r, n, l, st, cnt, dvel, Wr, k, x_begin, y_begin, lh_min, n_max,
+                           params, lh, flux, keep, index, n_obs, n_out, stream);
+}
+
+extern "C" kbm_status kbm_extract_top_noalloc(const kbm_results *r, int32_t Hr, int32_t Wr,
+                                              int32_t k, int32_t x_begin, int32_t y_begin,
+                                              const float *vel_dev, int32_t num_vel,
+                                              float lh_min, int64_t n_max, float *params,
+                                              float *lh, float *flux, uint64_t *keep,
+                                              int64_t *index, int16_t *n_obs,
+                                              int64_t *n_out, hipStream_t stream) {
+    using namespace kbm;
+    clear_error();
+    uint64_t n = 0;
+    kbm_status s = check_extract("kbm_extract_top_noalloc", r, Hr, Wr, k, vel_dev, num_vel,
+                                 lh_min, n_max, params, lh, flux, keep, n_obs, n_out, &n);
+    if (s != KBM_OK) return s;
+    const ExLayout l = ex_layout(n, num_vel);
+    KBM_REQUIRE(l.vel_off <= EX_SCRATCH_BYTES, KBM_ERR_UNSUPPORTED,
+                "kbm_extract_top_noalloc: %zu bytes of scratch needed, %zu available",
+                l.vel_off, EX_SCRATCH_BYTES);
+    char *ws = nullptr;
+    s = scratch_address(&ws);
+    if (s != KBM_OK) return s;
+    ExtractState *st = reinterpret_cast<ExtractState *>(ws + l.st_off);
+    unsigned int *cnt = reinterpret_cast<unsigned int *>(ws + l.cnt_off);
+    return enqueue_extract(r, n, l, st, cnt, vel_dev, Wr, k, x_begin, y_begin, lh_min,
+                           n_max, params, lh, flux, keep, index, n_obs, n_out, stream);
 }
