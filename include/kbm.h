@@ -186,7 +186,9 @@ typedef struct {
                               super-tiles, 4 waves, all that fit, sweep 1 if
                               some stack has >= 16384 velocities else 0 */
 #define KBM_TUNE_AUTO 1    /* time candidate schedules on a probe, keep the
-                              fastest (cached per process by batch shape) */
+                              fastest; cached per process and in a file by
+                              library build id, GPU architecture and batch
+                              shape (see kbm_tune_cache_clear) */
 #define KBM_TUNE_GIVEN 2   /* use *schedule as given */
 
 typedef struct kbm_batch kbm_batch; /* opaque plan with its captured graph */
@@ -234,6 +236,13 @@ kbm_status kbm_batch_check(kbm_batch *b, hipStream_t stream, int32_t *stalled);
  * kernel skipped because no start pixel of the tile can keep min_obs epochs
  * inside the image (their slots are empty either way). */
 kbm_status kbm_batch_evaluated(kbm_batch *b, hipStream_t stream, uint64_t *traj_epochs);
+
+/* Forget the autotuner's choices held in this process.  The choices also
+ * persist in a JSON file, KBM_TUNE_CACHE if that environment variable is
+ * set (empty: no file), else $HOME/.cache/kbm/autotune.json; a later
+ * KBM_TUNE_AUTO plan of a shape found there uses the stored schedule and
+ * probe time without tuning again.  Delete the file to re-tune. */
+kbm_status kbm_tune_cache_clear(void);
 
 /* Release the plan (graph, stream, host buffers); NULL is a no-op. */
 kbm_status kbm_batch_destroy(kbm_batch *b);
@@ -313,6 +322,28 @@ kbm_status kbm_refine(const kbm_stack *s, const float *psi, const float *phi,
                       float *grad_psi, float *grad_phi, hipStream_t stream);
 
 /*
+ * kbm_refine_adam - the refinement loop in one launch: `steps` gradient-
+ * ascent steps of Adam (Kingma & Ba 2015) on the likelihood of kbm_refine,
+ * then L at the final parameters.  Candidates are independent, so each
+ * lane runs its candidate's whole loop with the Adam moments in registers;
+ * the result equals, bit for bit, alternating kbm_refine (upstream gradient
+ * 1) and kbm_adam_step (maximize, step k) for k = 1 .. steps, then
+ * kbm_refine forward.  (Not a step of the paper: it refines search
+ * candidates to sub-pixel starts and real-valued velocities.)
+ *
+ *   params : device float [n][4] (x0, y0, vx, vy), updated in place
+ *   keep   : device uint64 [n]; NULL = all epochs
+ *   lr     : host float [steps][4], the step size of each step and column
+ *   steps  : 1 .. 64 (KBM_ERR_UNSUPPORTED above)
+ *   beta1, beta2, eps : as kbm_adam_step
+ *   lh     : device float [n], written: L at the returned params
+ */
+kbm_status kbm_refine_adam(const kbm_stack *s, const float *psi, const float *phi,
+                           int64_t n, float *params, const uint64_t *keep,
+                           const float *lr, int32_t steps, double beta1,
+                           double beta2, double eps, float *lh, hipStream_t stream);
+
+/*
  * kbm_score_trajectories - targeted evaluation: the search's filtered
  * likelihood (Section 3, 3.1) for an explicit list of linear trajectories
  * with real-valued starts, e.g. refined candidates or known objects.
@@ -369,6 +400,19 @@ kbm_status kbm_stamps(const kbm_stack *s, const float *sci, const float *var,
                       const uint64_t *keep, int32_t radius,
                       const double *limits, float *coadd, double *moments,
                       uint8_t *pass, hipStream_t stream);
+
+/*
+ * kbm_detect - the decision of the targeted (known-object) mode: trajectory
+ * j is detected when n_obs[j] >= min_obs, lh[j] >= lh_min (the paper keeps
+ * trajectories whose recomputed likelihood clears a threshold, Section 3.1)
+ * and its coadded stamp passes the moment cut (Section 3.3).  NaN lh never
+ * passes.
+ *   lh: device float [n]; n_obs: device int16 [n]; stamp_pass: device
+ *   uint8 [n]; detected: device uint8 [n], written (0 or 1)
+ */
+kbm_status kbm_detect(int64_t n, const float *lh, const int16_t *n_obs,
+                      const uint8_t *stamp_pass, int32_t min_obs, float lh_min,
+                      uint8_t *detected, hipStream_t stream);
 
 /*
  * kbm_extract_top - candidate extraction: the global top-N result slots by

@@ -29,7 +29,7 @@ __all__ = [
     "MAX_PSF", "extract_top", "adam_step", "refine", "BatchedSearch",
     "Schedule", "batch_workspace_size", "extract_workspace_size",
     "score_trajectories", "stamps", "STAMP_LIMITS", "sigmag_filter_ex", "sigmag_coeff",
-    "extract_top_noalloc", "Refiner",
+    "extract_top_noalloc", "Refiner", "detect", "tune_cache_clear", "refine_adam",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -96,6 +96,7 @@ def lib():
         L.kbm_sigmag_filter.argtypes = [P, P, P, i64, i32, f64, f64, f64, f64,
                                         P, P, P]
         L.kbm_refine.argtypes = [P, P, P, i64, P, P, P, P, P, P, P, P]
+        L.kbm_refine_adam.argtypes = [P, P, P, i64, P, P, P, i32, f64, f64, f64, P, P]
         L.kbm_extract_workspace_size.argtypes = [i32, i32, i32, i32, P]
         L.kbm_extract_top.argtypes = [P, i32, i32, i32, i32, i32, P, i32,
                                       C.c_float, i64, P, P, P, P, P, P, P, P,
@@ -111,12 +112,14 @@ def lib():
         L.kbm_batch_check.argtypes = [P, P, P]
         L.kbm_batch_evaluated.argtypes = [P, P, P]
         L.kbm_batch_destroy.argtypes = [P]
+        L.kbm_tune_cache_clear.argtypes = []
         L.kbm_score_trajectories.argtypes = [P, P, P, i64, P, i32, i32, f64, f64,
                                              f64, f64, P, P, P, P, P, P]
         L.kbm_stamps.argtypes = [P, P, P, P, i64, P, P, i32, P, P, P, P, P]
         L.kbm_sigmag_filter_ex.argtypes = [P, P, P, i64, i32, i32, f64, f64, f64, f64,
                                            f64, P, P, P, P]
         L.kbm_sigmag_coeff.argtypes = [f64, f64, P]
+        L.kbm_detect.argtypes = [i64, P, P, P, i32, C.c_float, P, P]
         _lib = L
         return L
 
@@ -351,6 +354,11 @@ def _batch_structs(items):
     return stacks, ps, hold
 
 
+def tune_cache_clear():
+    """Forget the autotuner's in-process choices (the file cache stays)."""
+    _check("kbm_tune_cache_clear", lib().kbm_tune_cache_clear())
+
+
 def batch_workspace_size(items) -> int:
     """Workspace bytes of a BatchedSearch over ``items`` (dicts with psi
     (or shape via a tensor), times, vels, params)."""
@@ -505,6 +513,20 @@ def sigmag_filter_ex(psi_curve, phi_curve=None, valid=None, quantity=0, q_lo=0.2
     return keep, lh, ok.bool()
 
 
+def detect(lh, n_obs, stamp_pass, min_obs, lh_min=10.0, stream=None):
+    """Targeted-mode decision per trajectory: n_obs >= min_obs, L' >= lh_min
+    and the stamp passes the moment cut (bool [n])."""
+    _dev(lh, torch.float32, "lh")
+    n = lh.shape[0]
+    _dev(n_obs, torch.int16, "n_obs", (n,))
+    sp = stamp_pass if stamp_pass.dtype == torch.uint8 else stamp_pass.to(torch.uint8)
+    _dev(sp, torch.uint8, "stamp_pass", (n,))
+    out = torch.empty(n, dtype=torch.uint8, device=lh.device)
+    _check("kbm_detect", lib().kbm_detect(n, _ptr(lh), _ptr(n_obs), _ptr(sp), int(min_obs),
+                                          float(lh_min), _ptr(out), _stream(stream)))
+    return out.bool()
+
+
 def sigmag_coeff(q_lo, q_hi) -> float:
     """C of Eq. 3 for a quantile pair (host computation in the library)."""
     c = C.c_double(0.0)
@@ -647,7 +669,7 @@ def stamps(sci, var, mask, times, params, keep=None, radius=10, limits=None,
     _check("kbm_stamps", lib().kbm_stamps(
         C.byref(st), _ptr(sci), _ptr(var), _ptr(mask), n, _ptr(prm), _ptr(keep),
         int(radius), lim, _ptr(coadd), _ptr(moments), _ptr(ok), _stream(stream)))
-    return dict(coadd=coadd, moments=moments, passed=ok.bool())
+    return dict(coadd=coadd, moments=moments, passed=ok.bool(), pass_u8=ok)
 
 
 def extract_workspace_size(Hr, Wr, k, num_vel) -> int:
@@ -747,6 +769,24 @@ def adam_step(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8,
         int(bool(maximize)), _stream(stream)))
 
 
+_lr_tables = {}
+
+
+def _refine_lr_table(times, steps, lr_pos, lr_vel, cosine):
+    """_refine_lrs as a float32 [steps][4] array, kept per schedule (the
+    refinement is called once per step of a search loop)."""
+    key = (tuple(np.asarray(times, np.float64).tolist()), int(steps), float(lr_pos),
+           None if lr_vel is None else float(lr_vel), bool(cosine))
+    tab = _lr_tables.get(key)
+    if tab is None:
+        tab = np.ascontiguousarray(
+            np.asarray(_refine_lrs(times, steps, lr_pos, lr_vel, cosine), np.float32))
+        if len(_lr_tables) > 64:
+            _lr_tables.clear()
+        _lr_tables[key] = tab
+    return tab
+
+
 def _refine_lrs(times, steps, lr_pos, lr_vel, cosine):
     """Per-step Adam step sizes [steps][4] of the refinement loop."""
     t = np.asarray(times, np.float64)
@@ -771,19 +811,55 @@ def _refine_steps(psi, phi, times, p, m, v, g, lh, ones, keep, lrs, stream):
     refine_forward(psi, phi, times, p, keep, stream=stream, out=lh)
 
 
+REFINE_MAX_FUSED_STEPS = 64
+
+
+def refine_adam(psi, phi, times, params, lrs, keep=None, beta1=0.9, beta2=0.999,
+                eps=1e-8, stream=None):
+    """The whole Adam loop in one kernel launch (kbm_refine_adam): updates
+    ``params`` [n][4] in place with the per-step step sizes ``lrs``
+    [steps][4] and returns L at the final parameters."""
+    _dev(psi, torch.float32, "psi")
+    _dev(phi, torch.float32, "phi", psi.shape)
+    _dev(params, torch.float32, "params")
+    T, H, W = psi.shape
+    n = params.shape[0]
+    if keep is not None:
+        _dev(keep, torch.int64, "keep", (n,))
+    lr = lrs if (isinstance(lrs, np.ndarray) and lrs.dtype == np.float32 and lrs.ndim == 2
+                 and lrs.shape[1] == 4 and lrs.flags.c_contiguous) \
+        else np.ascontiguousarray(np.asarray(lrs, np.float32).reshape(-1, 4))
+    st, _t = _stack(T, H, W, times)
+    lh = torch.empty(n, dtype=torch.float32, device=psi.device)
+    _check("kbm_refine_adam", lib().kbm_refine_adam(
+        C.byref(st), _ptr(psi), _ptr(phi), n, _ptr(params), _ptr(keep),
+        lr.ctypes.data_as(C.c_void_p), lr.shape[0], beta1, beta2, eps, _ptr(lh),
+        _stream(stream)))
+    return lh
+
+
 def refine(psi, phi, times, params0, keep=None, steps=50, lr_pos=0.3,
-           lr_vel=None, cosine=True, stream=None, graph=True):
+           lr_vel=None, cosine=True, stream=None, mode="fused"):
     """Gradient-ascent refinement of candidates with the bilinear adjoint.
 
-    Each step runs the adjoint kernel (L and dL/dparams) and one Adam update
-    kernel.  Position steps are ``lr_pos`` pixels; velocity steps default to
+    Each step runs the adjoint (L and dL/dparams) and one Adam update.
+    Position steps are ``lr_pos`` pixels; velocity steps default to
     ``lr_pos / t_span`` px/day so that both move the track by similar
-    amounts.  A cosine decay scales both.  With ``graph`` the loop is
-    replayed from a HIP graph captured once per problem (see Refiner);
-    otherwise its kernels are launched one by one.  Both run the same
-    kernels with the same arguments in the same order.  Returns (params, lh)
-    where lh is the likelihood at the returned params."""
-    if graph:
+    amounts.  A cosine decay scales both.  ``mode``: "fused" runs the whole
+    loop in one kernel launch (up to 64 steps; more fall back to "graph"),
+    "graph" replays the per-step adjoint and Adam kernels from a HIP graph
+    captured once per problem (see Refiner), "eager" launches them one by
+    one.  All three give the same bits.  Returns (params, lh) where lh is the
+    likelihood at the returned params."""
+    if mode not in ("fused", "graph", "eager"):
+        raise ValueError(f"mode must be fused, graph or eager, not {mode!r}")
+    if mode == "fused" and steps <= REFINE_MAX_FUSED_STEPS:
+        p = params0.detach().clone().contiguous()
+        lh = refine_adam(psi, phi, times, p,
+                         _refine_lr_table(times, steps, lr_pos, lr_vel, cosine), keep,
+                         stream=stream)
+        return p, lh
+    if mode != "eager":
         r = _refiner_for(psi, phi, times, params0.shape[0], keep is not None, steps,
                          lr_pos, lr_vel, cosine)
         p, lh = r.run(params0.contiguous(), keep, stream=stream)

@@ -26,8 +26,16 @@
 //  * The item of a tile's last block re-evaluates the K winners and writes
 //    the results.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <iomanip>
 #include <map>
+#include <sstream>
+
+#include <sys/stat.h>
+#include <unistd.h>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -67,6 +75,9 @@ bool pow2_in(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
 // DECam-CCD stack (2048 x 4096, T = 26, 128^2 velocities) takes 1183 ms this
 // way (interleaved: 1236 ms at its best block, 2048); 62 stacks of 64^2
 // velocities take 10.54 s (contiguous: 10.76 s at its best block, 512).
+static_assert(EVAL_SLOTS == srch::EVAL_SLOTS_N && EVAL_STRIDE == srch::EVAL_STRIDE_U64,
+              "evaluated-count layout of the control block");
+
 Sched default_sched(int vmax) { return Sched{1024, 2, 32, 4, 0, vmax >= 16384 ? 1 : 0}; }
 
 }  // namespace batch
@@ -285,8 +296,73 @@ kbm_status probe(kbm_batch *b, Sched sc, int div, hipStream_t stream,
 std::mutex g_tune_mutex;
 std::map<std::string, std::pair<Sched, float>> g_tuned;
 
+// Persisted choices of the autotuner: a JSON object mapping a key (library
+// build id, device architecture, batch shape) to [vel_block, tile_cols,
+// tile_rows, waves, blocks_per_cu, sweep, probe_ms], one entry per line.
+// The file is KBM_TUNE_CACHE if set (empty: no file), else
+// $HOME/.cache/kbm/autotune.json.  It is read and rewritten under the tune
+// mutex; a missing, unreadable or malformed file only costs a new tuning.
+std::string tune_cache_path() {
+    const char *e = std::getenv("KBM_TUNE_CACHE");
+    if (e) return std::string(e);
+    const char *h = std::getenv("HOME");
+    if (!h || !*h) return std::string();
+    return std::string(h) + "/.cache/kbm/autotune.json";
+}
+
+std::map<std::string, std::pair<Sched, float>> read_tune_cache(const std::string &path) {
+    std::map<std::string, std::pair<Sched, float>> m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
+        const size_t b0 = line.find('[', q1 == std::string::npos ? 0 : q1);
+        const size_t b1 = line.find(']', b0 == std::string::npos ? 0 : b0);
+        if (q0 == std::string::npos || q1 == std::string::npos || b0 == std::string::npos ||
+            b1 == std::string::npos)
+            continue;
+        std::string nums = line.substr(b0 + 1, b1 - b0 - 1);
+        std::replace(nums.begin(), nums.end(), ',', ' ');
+        std::istringstream is(nums);
+        Sched sc{};
+        float ms = 0.0f;
+        if (!(is >> sc.vb >> sc.st_x >> sc.st_y >> sc.nw >> sc.bpc >> sc.sw >> ms)) continue;
+        if (check_sched(sc) != KBM_OK) continue;
+        m[line.substr(q0 + 1, q1 - q0 - 1)] = std::make_pair(sc, ms);
+    }
+    clear_error();  // a rejected entry is not the caller's error
+    return m;
+}
+
+void write_tune_cache(const std::string &path,
+                      const std::map<std::string, std::pair<Sched, float>> &m) {
+    for (size_t i = 1; i < path.size(); ++i)  // the directories above the file
+        if (path[i] == '/') (void)::mkdir(path.substr(0, i).c_str(), 0755);
+    const std::string tmp = path + ".tmp" + std::to_string((long long)::getpid());
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        f << std::setprecision(9) << "{\n";
+        size_t i = 0;
+        for (const auto &kv : m) {
+            const Sched &c = kv.second.first;
+            f << "\"" << kv.first << "\": [" << c.vb << ", " << c.st_x << ", " << c.st_y
+              << ", " << c.nw << ", " << c.bpc << ", " << c.sw << ", " << kv.second.second
+              << "]" << (++i < m.size() ? "," : "") << "\n";
+        }
+        f << "}\n";
+        if (!f) return;
+    }
+    (void)std::rename(tmp.c_str(), path.c_str());
+}
+
 std::string shape_key(const kbm_batch *b, const kbm_search_params *p) {
-    std::string k = "dev" + std::to_string(b->device);
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == '"' || c == '\\') c = '_';
+    std::string k = std::string(kbm_build_id()) + "|" + arch;
     for (int j = 0; j < b->S; ++j) {
         k += "|" + std::to_string(b->Wr[j]) + "x" + std::to_string(b->Hr[j]) + "T" +
              std::to_string(b->T[j]) + "V" + std::to_string(b->V[j]) + "k" +
@@ -301,9 +377,15 @@ std::string shape_key(const kbm_batch *b, const kbm_search_params *p) {
 kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream,
                     Sched *best, float *best_ms) {
     const std::string key = shape_key(b, p);
+    const std::string cache = tune_cache_path();
     {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         auto it = g_tuned.find(key);
+        if (it == g_tuned.end() && !cache.empty()) {
+            auto disk = read_tune_cache(cache);
+            auto d = disk.find(key);
+            if (d != disk.end()) it = g_tuned.insert(*d).first;
+        }
         if (it != g_tuned.end()) {
             *best = it->second.first;
             *best_ms = it->second.second;
@@ -377,6 +459,11 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
     *best_ms = cur_ms;
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     g_tuned[key] = std::make_pair(cur, cur_ms);
+    if (!cache.empty()) {
+        auto disk = read_tune_cache(cache);
+        disk[key] = std::make_pair(cur, cur_ms);
+        write_tune_cache(cache, disk);
+    }
     return KBM_OK;
 }
 
@@ -561,7 +648,8 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
     st = write_schedule(b, sc, 1, stream);
     if (st != KBM_OK) return fail(st);
 
-    if (hipHostMalloc(&b->host_word, 64, hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc(&b->host_word, sizeof(uint64_t) * EVAL_SLOTS * EVAL_STRIDE,
+                      hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
         set_error("kbm_batch_create: cannot create the capture stream");
         return fail(KBM_ERR_DEVICE);
@@ -624,12 +712,24 @@ extern "C" kbm_status kbm_batch_evaluated(kbm_batch *b, hipStream_t stream,
     clear_error();
     KBM_REQUIRE(b != nullptr && traj_epochs != nullptr, KBM_ERR_INVALID_ARG,
                 "kbm_batch_evaluated: batch and traj_epochs must be non-NULL");
-    KBM_HIP(hipMemcpyAsync(b->host_word, b->ctrl + batch::CTRL_EVALS, sizeof(uint64_t),
+    const size_t n = (size_t)batch::EVAL_SLOTS * batch::EVAL_STRIDE;
+    KBM_HIP(hipMemcpyAsync(b->host_word, b->ctrl + batch::CTRL_EVALS, sizeof(uint64_t) * n,
                            hipMemcpyDeviceToHost, stream));
     KBM_HIP(hipStreamSynchronize(stream));
-    uint64_t v = 0;
-    std::memcpy(&v, b->host_word, sizeof(v));
-    *traj_epochs = v;
+    uint64_t total = 0;
+    for (int j = 0; j < batch::EVAL_SLOTS; ++j) {
+        uint64_t v = 0;
+        std::memcpy(&v, b->host_word + 2 * (size_t)j * batch::EVAL_STRIDE, sizeof(v));
+        total += v;
+    }
+    *traj_epochs = total;
+    return KBM_OK;
+}
+
+extern "C" kbm_status kbm_tune_cache_clear(void) {
+    kbm::clear_error();
+    std::lock_guard<std::mutex> lk(kbm::batch::g_tune_mutex);
+    kbm::batch::g_tuned.clear();
     return KBM_OK;
 }
 

@@ -3,12 +3,13 @@
 //
 // One lane per candidate.  Positions x_i = x0 + vx t_i are formed in FP64
 // (a float32 position at x ~ 4000 px would carry ~2e-4 px of rounding), the
-// taps and weights in binary32.  The forward pass accumulates the bilinear
-// samples of psi and phi over the kept epochs; the backward pass (only when
-// an upstream gradient is given) revisits the same taps, forms
-// dL/dx_i = dPsi/dx_i / sqrt(Phi) - L/(2 Phi) dPhi/dx_i, chains through
-// dx_i/dx0 = 1 and dx_i/dvx = t_i, and scatter-adds g/sqrt(Phi) * w_tap into
-// dL/dpsi and -g L/(2 Phi) * w_tap into dL/dphi with float atomics.
+// taps and weights in binary32.  One pass over the kept epochs accumulates
+// the bilinear samples of psi and phi and, when an upstream gradient is
+// given, the sums of their x and y derivatives (plain and times t_i), from
+// which dL/dx_i = dPsi/dx_i / sqrt(Phi) - L/(2 Phi) dPhi/dx_i chained through
+// dx_i/dx0 = 1 and dx_i/dvx = t_i follows; a second pass, only for plane
+// gradients, scatter-adds g/sqrt(Phi) * w_tap into dL/dpsi and
+// -g L/(2 Phi) * w_tap into dL/dphi with float atomics.
 #include "kbm_internal.h"
 
 namespace kbm {
@@ -59,44 +60,27 @@ __device__ __forceinline__ float tap(const float *plane, int W, int H, int x,
                : 0.0f;
 }
 
-__global__ __launch_bounds__(256) void refine_kernel(RefineArgs a) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.n) return;
-    const double x0 = a.params[4 * c + 0], y0 = a.params[4 * c + 1];
-    const double vx = a.params[4 * c + 2], vy = a.params[4 * c + 3];
-    const uint64_t km = a.keep ? a.keep[c] : ~(uint64_t)0;
+// L and (with `grad`) g * dL/dparams of candidate c at parameters (x0, y0,
+// vx, vy), plus the scatter-adds into the plane gradients when requested.
+// Returns L (0 when the kept samples carry no phi, with a zero gradient).
+//
+// dL/dx_i = A dPsi/dx_i + B dPhi/dx_i with A = 1/sqrt(Phi), B = -L/(2 Phi)
+// known only after the sums, but the parameter gradient is linear in the
+// per-epoch derivatives: dL/dx0 = A sum dPsi/dx_i + B sum dPhi/dx_i and
+// dL/dvx = A sum t_i dPsi/dx_i + B sum t_i dPhi/dx_i.  So one pass over
+// the taps accumulates the likelihood sums and these eight derivative sums;
+// only the plane-gradient scatter (which needs A and B per tap) revisits
+// the taps.
+__device__ __forceinline__ float refine_one(const RefineArgs &a, int64_t c, float px0,
+                                            float py0, float pvx, float pvy, uint64_t km,
+                                            bool grad, float g, float (&gp)[4]) {
+    const double x0 = px0, y0 = py0;
+    const double vx = pvx, vy = pvy;
     const size_t HW = (size_t)a.W * a.H;
 
     float Ps = 0.0f, Fs = 0.0f;
-    for (int i = 0; i < a.T; ++i) {
-        if (!((km >> i) & 1)) continue;
-        const Taps p = taps_at(a, x0, vx, y0, vy, a.t[i]);
-        if (!p.any) continue;
-        const float *ps = a.psi + i * HW;
-        const float *ph = a.phi + i * HW;
-        const float w00 = (1.0f - p.fx) * (1.0f - p.fy), w10 = p.fx * (1.0f - p.fy);
-        const float w01 = (1.0f - p.fx) * p.fy, w11 = p.fx * p.fy;
-        Ps += w00 * tap(ps, a.W, a.H, p.ix, p.iy) + w10 * tap(ps, a.W, a.H, p.ix + 1, p.iy) +
-              w01 * tap(ps, a.W, a.H, p.ix, p.iy + 1) + w11 * tap(ps, a.W, a.H, p.ix + 1, p.iy + 1);
-        Fs += w00 * tap(ph, a.W, a.H, p.ix, p.iy) + w10 * tap(ph, a.W, a.H, p.ix + 1, p.iy) +
-              w01 * tap(ph, a.W, a.H, p.ix, p.iy + 1) + w11 * tap(ph, a.W, a.H, p.ix + 1, p.iy + 1);
-    }
-    if (!(Fs > 0.0f)) {
-        a.lh[c] = 0.0f;
-        if (a.grad_lh) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) a.grad_params[4 * c + j] = 0.0f;
-        }
-        return;
-    }
-    const float L = Ps / sqrtf(Fs);
-    a.lh[c] = L;
-    if (!a.grad_lh) return;
-
-    const float g = a.grad_lh[c];
-    const float A = 1.0f / sqrtf(Fs);
-    const float B = -L / (2.0f * Fs);
-    float gx0 = 0.0f, gy0 = 0.0f, gvx = 0.0f, gvy = 0.0f;
+    float spx = 0.0f, spy = 0.0f, sfx = 0.0f, sfy = 0.0f;  // sums of dPsi, dPhi
+    float tpx = 0.0f, tpy = 0.0f, tfx = 0.0f, tfy = 0.0f;  // the same times t_i
     for (int i = 0; i < a.T; ++i) {
         if (!((km >> i) & 1)) continue;
         const Taps p = taps_at(a, x0, vx, y0, vy, a.t[i]);
@@ -107,18 +91,45 @@ __global__ __launch_bounds__(256) void refine_kernel(RefineArgs a) {
         const float s01 = tap(ps, a.W, a.H, p.ix, p.iy + 1), s11 = tap(ps, a.W, a.H, p.ix + 1, p.iy + 1);
         const float f00 = tap(ph, a.W, a.H, p.ix, p.iy), f10 = tap(ph, a.W, a.H, p.ix + 1, p.iy);
         const float f01 = tap(ph, a.W, a.H, p.ix, p.iy + 1), f11 = tap(ph, a.W, a.H, p.ix + 1, p.iy + 1);
-        const float dpx = (1.0f - p.fy) * (s10 - s00) + p.fy * (s11 - s01);
-        const float dpy = (1.0f - p.fx) * (s01 - s00) + p.fx * (s11 - s10);
-        const float dfx = (1.0f - p.fy) * (f10 - f00) + p.fy * (f11 - f01);
-        const float dfy = (1.0f - p.fx) * (f01 - f00) + p.fx * (f11 - f10);
-        const float dx = A * dpx + B * dfx;
-        const float dy = A * dpy + B * dfy;
-        const float ti = (float)a.t[i];
-        gx0 += dx;
-        gy0 += dy;
-        gvx += ti * dx;
-        gvy += ti * dy;
-        if (a.grad_psi || a.grad_phi) {
+        const float w00 = (1.0f - p.fx) * (1.0f - p.fy), w10 = p.fx * (1.0f - p.fy);
+        const float w01 = (1.0f - p.fx) * p.fy, w11 = p.fx * p.fy;
+        Ps += w00 * s00 + w10 * s10 + w01 * s01 + w11 * s11;
+        Fs += w00 * f00 + w10 * f10 + w01 * f01 + w11 * f11;
+        if (grad) {
+            const float dpx = (1.0f - p.fy) * (s10 - s00) + p.fy * (s11 - s01);
+            const float dpy = (1.0f - p.fx) * (s01 - s00) + p.fx * (s11 - s10);
+            const float dfx = (1.0f - p.fy) * (f10 - f00) + p.fy * (f11 - f01);
+            const float dfy = (1.0f - p.fx) * (f01 - f00) + p.fx * (f11 - f10);
+            const float ti = (float)a.t[i];
+            spx += dpx;
+            spy += dpy;
+            sfx += dfx;
+            sfy += dfy;
+            tpx += ti * dpx;
+            tpy += ti * dpy;
+            tfx += ti * dfx;
+            tfy += ti * dfy;
+        }
+    }
+    if (!(Fs > 0.0f)) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gp[j] = 0.0f;
+        return 0.0f;
+    }
+    const float L = Ps / sqrtf(Fs);
+    if (!grad) return L;
+
+    const float A = 1.0f / sqrtf(Fs);
+    const float B = -L / (2.0f * Fs);
+    gp[0] = g * (A * spx + B * sfx);
+    gp[1] = g * (A * spy + B * sfy);
+    gp[2] = g * (A * tpx + B * tfx);
+    gp[3] = g * (A * tpy + B * tfy);
+    if (a.grad_psi || a.grad_phi) {
+        for (int i = 0; i < a.T; ++i) {
+            if (!((km >> i) & 1)) continue;
+            const Taps p = taps_at(a, x0, vx, y0, vy, a.t[i]);
+            if (!p.any) continue;
             const float w[4] = {(1.0f - p.fx) * (1.0f - p.fy), p.fx * (1.0f - p.fy),
                                 (1.0f - p.fx) * p.fy, p.fx * p.fy};
             const int xs[4] = {p.ix, p.ix + 1, p.ix, p.ix + 1};
@@ -132,10 +143,71 @@ __global__ __launch_bounds__(256) void refine_kernel(RefineArgs a) {
             }
         }
     }
-    a.grad_params[4 * c + 0] = g * gx0;
-    a.grad_params[4 * c + 1] = g * gy0;
-    a.grad_params[4 * c + 2] = g * gvx;
-    a.grad_params[4 * c + 3] = g * gvy;
+    return L;
+}
+
+__global__ __launch_bounds__(256) void refine_kernel(RefineArgs a) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n) return;
+    const uint64_t km = a.keep ? a.keep[c] : ~(uint64_t)0;
+    const bool grad = a.grad_lh != nullptr;
+    float gp[4];
+    const float L = refine_one(a, c, a.params[4 * c + 0], a.params[4 * c + 1],
+                               a.params[4 * c + 2], a.params[4 * c + 3], km, grad,
+                               grad ? a.grad_lh[c] : 0.0f, gp);
+    a.lh[c] = L;
+    if (!grad) return;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a.grad_params[4 * c + j] = gp[j];
+}
+
+// The whole refinement loop for one candidate per lane: `steps` times the
+// adjoint (upstream gradient 1) and the Adam update of the four parameters
+// with m and v in registers, then L at the final parameters.  Each step's
+// arithmetic is that of refine_kernel followed by adam_kernel, so the
+// result equals alternating the two launches, bit for bit.
+constexpr int REFINE_MAX_STEPS = 64;
+struct RefineAdamArgs {
+    RefineArgs r;   // params and lh alias the in/out arrays below
+    float *params;  // [n][4], updated in place
+    float lr[REFINE_MAX_STEPS][4];
+    float c1[REFINE_MAX_STEPS], c2[REFINE_MAX_STEPS];  // 1 - beta^step
+    float b1, b2, omb1, omb2, eps;
+    int steps;
+};
+
+// 64-lane workgroups: 10^5 candidates make ~1560 waves, which spread over
+// the 256 CUs far more evenly as single waves than as groups of four.
+constexpr int REFINE_ADAM_THREADS = 64;
+__global__ __launch_bounds__(REFINE_ADAM_THREADS) void refine_adam_kernel(RefineAdamArgs a) {
+#pragma clang fp contract(off)
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.r.n) return;
+    const uint64_t km = a.r.keep ? a.r.keep[c] : ~(uint64_t)0;
+    float p[4], m[4], v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        p[j] = a.params[4 * c + j];
+        m[j] = 0.0f;
+        v[j] = 0.0f;
+    }
+    for (int s = 0; s < a.steps; ++s) {
+        float gp[4];
+        (void)refine_one(a.r, c, p[0], p[1], p[2], p[3], km, true, 1.0f, gp);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float g = -1.0f * gp[j];  // ascent: the gradient of -L
+            m[j] = a.b1 * m[j] + a.omb1 * g;
+            v[j] = a.b2 * v[j] + a.omb2 * g * g;
+            const float mh = m[j] / a.c1[s], vh = v[j] / a.c2[s];
+            p[j] -= a.lr[s][j] * mh / (sqrtf(vh) + a.eps);
+        }
+    }
+    float gp[4];
+    const float L = refine_one(a.r, c, p[0], p[1], p[2], p[3], km, false, 0.0f, gp);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a.params[4 * c + j] = p[j];
+    a.r.lh[c] = L;
 }
 
 }  // namespace
@@ -181,6 +253,63 @@ extern "C" kbm_status kbm_refine(const kbm_stack *s, const float *psi,
     hipLaunchKernelGGL(refine_kernel, dim3((unsigned)((n + 255) / 256)),
                        dim3(256), 0, stream, a);
     KBM_LAUNCHED("refine_kernel");
+    return KBM_OK;
+}
+
+extern "C" kbm_status kbm_refine_adam(const kbm_stack *s, const float *psi,
+                                      const float *phi, int64_t n, float *params,
+                                      const uint64_t *keep, const float *lr, int32_t steps,
+                                      double beta1, double beta2, double eps, float *lh,
+                                      hipStream_t stream) {
+    using namespace kbm;
+    clear_error();
+    kbm_status st = check_stack(s, "kbm_refine_adam");
+    if (st != KBM_OK) return st;
+    KBM_REQUIRE(n >= 0, KBM_ERR_INVALID_ARG, "kbm_refine_adam: n = %lld must be >= 0",
+                (long long)n);
+    KBM_REQUIRE(steps >= 1 && steps <= REFINE_MAX_STEPS, KBM_ERR_UNSUPPORTED,
+                "kbm_refine_adam: steps = %d not in [1, %d]", steps, REFINE_MAX_STEPS);
+    KBM_REQUIRE(lr != nullptr, KBM_ERR_INVALID_ARG, "kbm_refine_adam: lr is NULL");
+    for (int j = 0; j < 4 * steps; ++j)
+        KBM_REQUIRE(std::isfinite(lr[j]), KBM_ERR_INVALID_ARG,
+                    "kbm_refine_adam: lr[%d] is not finite", j);
+    KBM_REQUIRE(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0,
+                KBM_ERR_INVALID_ARG, "kbm_refine_adam: bad betas or eps");
+    KBM_REQUIRE(n == 0 || (psi && phi && params && lh), KBM_ERR_INVALID_ARG,
+                "kbm_refine_adam: psi, phi, params and lh must be non-NULL");
+    KBM_REQUIRE((n + 63) / 64 < ((int64_t)1 << 31), KBM_ERR_UNSUPPORTED,
+                "kbm_refine_adam: n = %lld too large", (long long)n);
+    if (n == 0) return KBM_OK;
+    RefineAdamArgs a{};
+    a.r.psi = psi;
+    a.r.phi = phi;
+    a.r.params = params;
+    a.r.keep = keep;
+    a.r.lh = lh;
+    a.r.n = n;
+    a.r.W = s->width;
+    a.r.H = s->height;
+    a.r.T = s->num_epochs;
+    double t0 = s->times[0];
+    for (int i = 1; i < a.r.T; ++i) t0 = std::min(t0, s->times[i]);
+    for (int i = 0; i < a.r.T; ++i) a.r.t[i] = s->times[i] - t0;
+    a.params = params;
+    for (int k = 0; k < steps; ++k) {
+        for (int j = 0; j < 4; ++j) a.lr[k][j] = lr[4 * k + j];
+        // as kbm_adam_step at step k + 1
+        a.c1[k] = (float)(1.0 - std::pow(beta1, (double)(k + 1)));
+        a.c2[k] = (float)(1.0 - std::pow(beta2, (double)(k + 1)));
+    }
+    a.b1 = (float)beta1;
+    a.b2 = (float)beta2;
+    a.omb1 = (float)(1.0 - beta1);
+    a.omb2 = (float)(1.0 - beta2);
+    a.eps = (float)eps;
+    a.steps = steps;
+    hipLaunchKernelGGL(refine_adam_kernel,
+                       dim3((unsigned)((n + REFINE_ADAM_THREADS - 1) / REFINE_ADAM_THREADS)),
+                       dim3(REFINE_ADAM_THREADS), 0, stream, a);
+    KBM_LAUNCHED("refine_adam_kernel");
     return KBM_OK;
 }
 

@@ -163,3 +163,35 @@ extern "C" kbm_status kbm_stamps(const kbm_stack *s, const float *sci, const flo
     KBM_LAUNCHED("stamp_kernel");
     return KBM_OK;
 }
+
+// Decision of the targeted mode: enough usable epochs, filtered likelihood
+// at least lh_min (NaN never passes), stamp passes the moment cut.
+namespace kbm {
+namespace {
+__global__ __launch_bounds__(256) void detect_kernel(int64_t n, const float *lh,
+                                                     const int16_t *n_obs,
+                                                     const uint8_t *stamp_pass, int min_obs,
+                                                     float lh_min, uint8_t *detected) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    detected[j] = (n_obs[j] >= min_obs && lh[j] >= lh_min && stamp_pass[j] != 0) ? 1 : 0;
+}
+}  // namespace
+}  // namespace kbm
+
+extern "C" kbm_status kbm_detect(int64_t n, const float *lh, const int16_t *n_obs,
+                                 const uint8_t *stamp_pass, int32_t min_obs, float lh_min,
+                                 uint8_t *detected, hipStream_t stream) {
+    using namespace kbm;
+    clear_error();
+    KBM_REQUIRE(n >= 0 && n < ((int64_t)1 << 40), KBM_ERR_INVALID_ARG,
+                "kbm_detect: n = %lld out of range", (long long)n);
+    KBM_REQUIRE(n == 0 || (lh && n_obs && stamp_pass && detected), KBM_ERR_INVALID_ARG,
+                "kbm_detect: arrays must be non-NULL");
+    KBM_REQUIRE(!std::isnan(lh_min), KBM_ERR_INVALID_ARG, "kbm_detect: lh_min is NaN");
+    if (n == 0) return KBM_OK;
+    hipLaunchKernelGGL(detect_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       n, lh, n_obs, stamp_pass, (int)min_obs, lh_min, detected);
+    KBM_LAUNCHED("detect_kernel");
+    return KBM_OK;
+}

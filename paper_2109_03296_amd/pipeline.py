@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import torch
 
-from . import (SearchParams, extract_top, extract_workspace_size, refine,
+from . import (SearchParams, detect, extract_top, extract_workspace_size, refine,
                score_trajectories, search, search_batched, stamps)
 
 
@@ -86,7 +86,8 @@ def known_objects(sci, var, mask, psi, phi, times, params, search_params: Search
                 want_coadd=False, stream=stream)
     ev[2].record(s)
     ev[2].synchronize()
-    det = (sc["n_obs"] >= search_params.min_obs) & (sc["lh"] >= lh_min) & st["passed"]
+    det = detect(sc["lh"], sc["n_obs"], st["pass_u8"], search_params.min_obs, lh_min,
+                 stream=stream)
     return dict(lh=sc["lh"], flux=sc["flux"], keep=sc["keep"], n_obs=sc["n_obs"],
                 moments=st["moments"], stamp_pass=st["passed"], detected=det,
                 ms=dict(score=ev[0].elapsed_time(ev[1]), stamps=ev[1].elapsed_time(ev[2])))

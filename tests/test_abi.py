@@ -262,3 +262,12 @@ def test_binding_rejects_host_tensors():
     x = torch.zeros(2, 4, 4)
     with pytest.raises(TypeError):
         kbm.make_planes(x, x, None, np.ones((3, 3), np.float32))
+
+
+def test_detect_validation(L):
+    L.kbm_detect.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                             C.c_float, C.c_void_p, C.c_void_p]
+    assert L.kbm_detect(-1, FAKE, FAKE, FAKE, 1, 10.0, FAKE, None) == 1
+    assert L.kbm_detect(5, None, FAKE, FAKE, 1, 10.0, FAKE, None) == 1
+    assert L.kbm_detect(5, FAKE, FAKE, FAKE, 1, float("nan"), FAKE, None) == 1
+    assert L.kbm_detect(0, None, None, None, 1, 10.0, None, None) == 0

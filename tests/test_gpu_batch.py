@@ -200,13 +200,32 @@ def test_batch_graph_replay_and_refill(kbm, batch):
             _equal(r, ref)
 
 
-def test_batch_autotune(kbm, batch):
+def test_batch_autotune(kbm, batch, tmp_path, monkeypatch):
+    """The autotuned schedule gives the per-stack results; its choice is
+    written to the cache file and, once the process forgets it, read back
+    (same schedule and probe time, no new tuning)."""
+    import json
+    cache = tmp_path / "kbm" / "autotune.json"
+    monkeypatch.setenv("KBM_TUNE_CACHE", str(cache))
+    kbm.tune_cache_clear()
     _say("batch: autotuned schedule")
     res, sched = _run(kbm, batch, kbm.TUNE_AUTO)
     _say(f"  tuned {sched}")
     assert sched["vel_block"] >= 32 and sched["waves"] in (1, 4)
     assert sched["blocks_per_cu"] >= 1 and sched["probe_ms"] > 0
     for b, r in zip(batch, res):
+        _equal(r, b["plain"])
+    stored = json.loads(cache.read_text())
+    assert len(stored) == 1
+    (key, val), = stored.items()
+    L = kbm.lib()
+    L.kbm_build_id.restype = __import__("ctypes").c_char_p
+    assert key.startswith(L.kbm_build_id().decode() + "|gfx950")
+    assert val[0] == sched["vel_block"] and val[5] == sched["sweep"]
+    kbm.tune_cache_clear()
+    res2, sched2 = _run(kbm, batch, kbm.TUNE_AUTO)
+    assert sched2 == sched
+    for b, r in zip(batch, res2):
         _equal(r, b["plain"])
 
 

@@ -383,10 +383,11 @@ def test_trajlh_plane_gradients_through_autograd(kbm, oracle_mod):
         assert np.allclose(got.cpu().numpy(), want, rtol=1e-4, atol=1e-5 * scale)
 
 
-def test_refine_graph_matches_eager(kbm, oracle_mod):
-    """The refinement loop replayed from its captured graph gives bit for bit
-    what the eager launches give, on several replays with other inputs and
-    eager work between them, with and without keep masks."""
+def test_refine_graph_and_fused_match_eager(kbm, oracle_mod):
+    """The refinement loop replayed from its captured graph, and the whole
+    loop run by one fused kernel launch, give bit for bit what the eager
+    launches give: several replays with other inputs and eager work between
+    them, with and without keep masks."""
     st, psi, phi, params, keep = _refine_setup(oracle_mod, n=700, seed=14)
     gpsi, gphi = _cuda(psi), _cuda(phi)
     rng = np.random.default_rng(15)
@@ -395,19 +396,27 @@ def test_refine_graph_matches_eager(kbm, oracle_mod):
     for rep in range(3):
         p0 = params + rng.normal(scale=0.3, size=params.shape).astype(np.float32)
         k0 = _cuda(keep.view(np.int64))
-        pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(p0), k0, steps=20, graph=False)
+        pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(p0), k0, steps=20, mode="eager")
         junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
         pg, lg = r.run(_cuda(p0), k0)
         torch.cuda.synchronize()
         assert torch.equal(pg, pe) and torch.equal(lg, le), rep
-        pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(p0), None, steps=20, graph=False)
+        pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(p0), None, steps=20, mode="eager")
         pg, lg = r0.run(_cuda(p0))
         torch.cuda.synchronize()
         assert torch.equal(pg, pe) and torch.equal(lg, le), rep
         del junk
-    # refine() itself goes through a cached graph by default
-    pd, ld = kbm.refine(gpsi, gphi, st.times, _cuda(params), None, steps=20)
-    pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(params), None, steps=20, graph=False)
+    for keep_t in (None, _cuda(keep.view(np.int64))):
+        pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(params), keep_t, steps=20,
+                            mode="eager")
+        for mode in ("graph", "fused"):
+            pm, lm = kbm.refine(gpsi, gphi, st.times, _cuda(params), keep_t, steps=20,
+                                mode=mode)
+            torch.cuda.synchronize()
+            assert torch.equal(pm, pe) and torch.equal(lm, le), mode
+    # the default (50 steps, fused) against the eager loop
+    pd, ld = kbm.refine(gpsi, gphi, st.times, _cuda(params))
+    pe, le = kbm.refine(gpsi, gphi, st.times, _cuda(params), mode="eager")
     assert torch.equal(pd, pe) and torch.equal(ld, le)
 
 
