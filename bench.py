@@ -459,6 +459,8 @@ def bench_ccd(args):
                             "basis": "8 B (nu, sqrt(phi)) per evaluated trajectory-epoch "
                                      "against the LDS bandwidth"},
     }
+    log("standalone filter and stamps on the extracted candidates")
+    rec.update(bench_filter_stamps(kbm, st, sci, var, mask, psi, phi, cand, prm))
     if not args.no_check:
         log("checking the batched results against the per-stack search")
         ref = kbm.search(psi, phi, st.times, st.vels, sp)
@@ -473,6 +475,67 @@ def bench_ccd(args):
         log("timing the CPU oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(st, prm, log)
     return rec
+
+
+def bench_filter_stamps(kbm, st, sci, var, mask, psi, phi, cand, prm, reps=40):
+    """The standalone sigma_G filter and the median stamps on the benchmark
+    stack's extracted candidates.  Filter: the candidates' lightcurves
+    (psi, phi along each grid trajectory) gathered into [n][T] rows and
+    repeated ``reps`` times; its keep masks must equal the ones the search's
+    fused filter gave the same trajectories.  Stamps: 21 x 21 median coadds
+    and the moment cut for the best 10^4 candidates.  Kernel spans from HIP
+    events."""
+    import torch
+    T, H, W = psi.shape
+    dev = psi.device
+    p = cand["params"]
+    t = torch.tensor(st.times - st.times.min(), dtype=torch.float64, device=dev)
+    # offsets floor(v t + 1/2) in FP64, rounded as the search rounds them
+    dx = torch.floor(p[:, 2:3].double() * t[None, :] + 0.5).long()
+    dy = torch.floor(p[:, 3:4].double() * t[None, :] + 0.5).long()
+    xs = p[:, 0:1].long() + dx
+    ys = p[:, 1:2].long() + dy
+    inside = (xs >= 0) & (xs < W) & (ys >= 0) & (ys < H)
+    ep = torch.arange(T, device=dev)[None, :].expand_as(xs)
+    flat = (ep * H + ys.clamp(0, H - 1)) * W + xs.clamp(0, W - 1)
+    cps = torch.where(inside, psi.reshape(-1)[flat], torch.zeros((), device=dev))
+    cph = torch.where(inside, phi.reshape(-1)[flat], torch.zeros((), device=dev))
+    valid = inside.to(torch.uint8)
+    n0 = cps.shape[0]
+    big_ps = cps.repeat(reps, 1).contiguous()
+    big_ph = cph.repeat(reps, 1).contiguous()
+    big_ok = valid.repeat(reps, 1).contiguous()
+    kbm.sigmag_filter_ex(big_ps, big_ph, big_ok, lh_min=10.0)   # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    keep, lh, ok = kbm.sigmag_filter_ex(big_ps, big_ph, big_ok, lh_min=10.0)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    n = big_ps.shape[0]
+    same = bool(torch.equal(keep[:n0], cand["keep"]))
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    m = min(10_000, n0)
+    sp = p[:m].contiguous()
+    kbm.stamps(sci, var, mask, st.times, sp, keep=cand["keep"][:m].contiguous(), radius=10,
+               want_coadd=False)
+    e2.record()
+    stp = kbm.stamps(sci, var, mask, st.times, sp, keep=cand["keep"][:m].contiguous(),
+                     radius=10, want_coadd=False)
+    e3.record()
+    e3.synchronize()
+    ms_st = e2.elapsed_time(e3)
+    return {"standalone_filter": {
+                "lightcurves": n, "epochs": T, "ms": ms,
+                "lightcurves_per_s": n / (ms / 1e3),
+                "gb_per_s": n * T * 9 / (ms / 1e3) / 1e9,
+                "bytes_per_lightcurve_epoch": 9,
+                "keep_equals_fused_filter": same,
+                "input": f"the {n0} extracted candidates' lightcurves (psi, phi, usable "
+                         f"flag along each grid trajectory), repeated {reps} times"},
+            "stamps": {"trajectories": m, "radius": 10, "epochs": T, "ms": ms_st,
+                       "trajectories_per_s": m / (ms_st / 1e3),
+                       "passed": int(stp["passed"].sum().item())}}
 
 
 def bench_batch62(args, steps, warmup):

@@ -1,5 +1,6 @@
 // Standalone sigma_G lightcurve filter (Section 3.1, Eqs. 1-5) over n
-// independent lightcurves, one lane per lightcurve.  Same rule, ranks and
+// independent lightcurves, one lane per lightcurve (rows staged through
+// LDS, below).  Same rule, ranks and
 // binary32 decision as the filter fused into the search kernel (the device
 // code is shared through kbm_internal.h).  The filtered per-epoch value is
 // the likelihood psi/sqrt(phi) or, as a variant the paper allows, the flux
@@ -10,27 +11,50 @@
 namespace kbm {
 namespace {
 
+// One 64-lane workgroup per 64 lightcurves.  Their rows are contiguous in
+// memory ([n][T]), so the workgroup first copies the whole 64 x T block of
+// psi, phi and the validity flags into LDS with coalesced loads (lane j
+// reads elements j, j + 64, ...), then each lane reads its own row from LDS
+// (row stride T rounded up to odd, so the 64 lanes hit 64 different banks).
+// Reading the rows directly would make every load instruction touch up to
+// 64 different cache lines.
+constexpr int SG_LANES = 64;
+
 template <int TM>
-__global__ __launch_bounds__(256) void sigmag_kernel(
+__global__ __launch_bounds__(SG_LANES) void sigmag_kernel(
     const float *__restrict__ psi, const float *__restrict__ phi,
     const uint8_t *__restrict__ valid, int64_t n, int T, int quantity, RankTable rt,
     float coeff, float n_sigma, float lh_min, uint64_t *__restrict__ keep,
     float *__restrict__ lh, uint8_t *__restrict__ pass) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
+    constexpr int RS = TM | 1;  // LDS row stride (odd)
+    __shared__ float s_ps[SG_LANES * RS];
+    __shared__ float s_ph[SG_LANES * RS];
+    __shared__ uint8_t s_ok[SG_LANES * RS];
+    const int64_t c0 = (int64_t)blockIdx.x * SG_LANES;
+    const int rows = (int)min((int64_t)SG_LANES, n - c0);
+    const int64_t base = c0 * T;
+    const int count = rows * T;
+    for (int j = threadIdx.x; j < count; j += SG_LANES) {
+        const int r = j / T, i = j - r * T;
+        s_ps[r * RS + i] = psi[base + j];
+        s_ph[r * RS + i] = phi ? phi[base + j] : 1.0f;
+        s_ok[r * RS + i] = valid ? valid[base + j] : (uint8_t)1;
+    }
+    __syncthreads();
+    const int l = threadIdx.x;
+    if (l >= rows) return;
+    const int64_t c = c0 + l;
     float ps[TM], ph[TM], nu[TM];
     int nv = 0;
-    const int64_t row = c * T;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         ps[i] = 0.0f;
         ph[i] = 0.0f;
         nu[i] = i < T ? __builtin_nanf("") : INFINITY;
         if (i < T) {
-            const float a = psi[row + i];
-            const float b = phi ? phi[row + i] : 1.0f;
-            const bool ok = (valid == nullptr || valid[row + i] != 0) &&
-                            b > 0.0f && isfinite(b) && isfinite(a);
+            const float a = s_ps[l * RS + i];
+            const float b = s_ph[l * RS + i];
+            const bool ok = s_ok[l * RS + i] != 0 && b > 0.0f && isfinite(b) && isfinite(a);
             if (ok) {
                 ps[i] = a;
                 ph[i] = b;
@@ -70,8 +94,8 @@ template <int TM>
 void launch(const float *psi, const float *phi, const uint8_t *valid,
             int64_t n, int T, int quantity, const RankTable &rt, float coeff, float ns,
             float lh_min, uint64_t *keep, float *lh, uint8_t *pass, hipStream_t stream) {
-    const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL((sigmag_kernel<TM>), dim3((unsigned)blocks), dim3(256),
+    const int64_t blocks = (n + SG_LANES - 1) / SG_LANES;
+    hipLaunchKernelGGL((sigmag_kernel<TM>), dim3((unsigned)blocks), dim3(SG_LANES),
                        0, stream, psi, phi, valid, n, T, quantity, rt, coeff, ns, lh_min,
                        keep, lh, pass);
 }
@@ -100,7 +124,7 @@ extern "C" kbm_status kbm_sigmag_filter_ex(const float *psi_curve, const float *
     KBM_REQUIRE(n == 0 || (psi_curve != nullptr && keep != nullptr),
                 KBM_ERR_INVALID_ARG,
                 "kbm_sigmag_filter: psi_curve and keep must be non-NULL");
-    KBM_REQUIRE((n + 255) / 256 < ((int64_t)1 << 31), KBM_ERR_UNSUPPORTED,
+    KBM_REQUIRE((n + 63) / 64 < ((int64_t)1 << 31), KBM_ERR_UNSUPPORTED,
                 "kbm_sigmag_filter: n = %lld too large", (long long)n);
     if (n == 0) return KBM_OK;
     const RankTable rt = make_rank_table(q_lo, q_hi);
