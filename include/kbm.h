@@ -230,11 +230,15 @@ kbm_status kbm_batch_run(kbm_batch *b, hipStream_t stream);
  * Each wait is bounded, so a run always ends. */
 kbm_status kbm_batch_check(kbm_batch *b, hipStream_t stream, int32_t *stalled);
 
-/* Synchronise `stream` and report how many trajectory-epochs (start pixel x
- * velocity x epoch) the last completed run evaluated: the nominal
- * W*H*V*T of every stack minus the (64-pixel row tile, velocity) pairs the
- * kernel skipped because no start pixel of the tile can keep min_obs epochs
- * inside the image (their slots are empty either way). */
+/* Report how many trajectory-epochs (start pixel x velocity x epoch) one run
+ * of the plan evaluates: the nominal W*H*V*T of every search region minus
+ * the (64-pixel row tile, velocity) pairs that the kernel skips because
+ * some epoch of the tile leaves the image and no start pixel of the tile can
+ * keep min_obs epochs inside it (their slots are empty either way).  The
+ * skip depends only on the geometry, so the count is fixed when the plan is
+ * created and computed on the host from the same offset tables the kernel
+ * reads (a counter inside the sweep would cost it registers); `stream` is
+ * not used. */
 kbm_status kbm_batch_evaluated(kbm_batch *b, hipStream_t stream, uint64_t *traj_epochs);
 
 /* Forget the autotuner's choices held in this process.  The choices also

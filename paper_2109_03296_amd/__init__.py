@@ -442,9 +442,10 @@ class BatchedSearch:
         return bool(stalled.value)
 
     def evaluated(self, stream=None) -> int:
-        """Synchronise and return the trajectory-epochs the last run
-        evaluated (the nominal count minus the tile-velocity pairs skipped
-        because no start pixel of the tile can keep min_obs epochs)."""
+        """Trajectory-epochs one run of the plan evaluates: the nominal count
+        minus the tile-velocity pairs the kernel skips because no start
+        pixel of the tile can keep min_obs epochs.  The skip depends only on
+        the geometry, so the library counts it when the plan is created."""
         n = C.c_uint64(0)
         _check("kbm_batch_evaluated", lib().kbm_batch_evaluated(
             self._h, _stream(stream), C.byref(n)))

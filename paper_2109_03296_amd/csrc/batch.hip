@@ -75,10 +75,44 @@ bool pow2_in(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
 // DECam-CCD stack (2048 x 4096, T = 26, 128^2 velocities) takes 1183 ms this
 // way (interleaved: 1236 ms at its best block, 2048); 62 stacks of 64^2
 // velocities take 10.54 s (contiguous: 10.76 s at its best block, 512).
-static_assert(EVAL_SLOTS == srch::EVAL_SLOTS_N && EVAL_STRIDE == srch::EVAL_STRIDE_U64,
-              "evaluated-count layout of the control block");
-
 Sched default_sched(int vmax) { return Sched{1024, 2, 32, 4, 0, vmax >= 16384 ? 1 : 0}; }
+
+// Trajectory-epochs that one run of a stack evaluates.  The sweep evaluates
+// a (tile, velocity) pair when every epoch of every lane of the tile's
+// 64-pixel row segment stays inside the image (F, the offset bounding box)
+// or when, per axis, min_obs epochs keep some lane inside (M, the min_obs
+// box), and skips it otherwise.  Both tests only depend on the geometry,
+// and each is a column condition and a row condition, so per velocity
+//   pairs(F or M) = pairs(F) + pairs(M) - pairs(F and M),
+// each term a lane count over the tile columns times a row count.  Padding
+// lanes of the last column tile are not counted.
+uint64_t evaluated_traj_epochs(const srch::SearchArgs &a, const int4 *box, const int4 *mbox) {
+    const int64_t y_lo = a.y0, y_hi = (int64_t)a.y0 + a.Hr - 1, H1 = (int64_t)a.H - 1;
+    auto rows = [&](int64_t lo, int64_t hi) -> int64_t {
+        lo = std::max(lo, y_lo);
+        hi = std::min(hi, y_hi);
+        return hi >= lo ? hi - lo + 1 : 0;
+    };
+    uint64_t pairs = 0;  // lane-weighted (pixel, velocity) pairs
+    for (int v = 0; v < a.V; ++v) {
+        const int4 bx = box[2 * v], mb = mbox[v];
+        int64_t lf = 0, lm = 0, lfm = 0;
+        for (int tx = 0; tx < a.tiles_x; ++tx) {
+            const int64_t xw = (int64_t)a.x0 + (int64_t)tx * WAVE;
+            const int64_t lanes = std::min<int64_t>(WAVE, (int64_t)a.Wr - (int64_t)tx * WAVE);
+            const bool fx = xw + bx.x >= 0 && xw + (WAVE - 1) + bx.y < a.W;
+            const bool mx = xw + mb.x <= a.W - 1 && xw + (WAVE - 1) + mb.y >= 0;
+            lf += fx ? lanes : 0;
+            lm += mx ? lanes : 0;
+            lfm += (fx && mx) ? lanes : 0;
+        }
+        const int64_t f_lo = -(int64_t)bx.z, f_hi = H1 - bx.w;  // y + bx.z >= 0, y + bx.w < H
+        const int64_t m_lo = -(int64_t)mb.w, m_hi = H1 - mb.z;  // y + mb.w >= 0, y + mb.z < H
+        pairs += (uint64_t)(lf * rows(f_lo, f_hi) + lm * rows(m_lo, m_hi) -
+                            lfm * rows(std::max(f_lo, m_lo), std::min(f_hi, m_hi)));
+    }
+    return pairs * (uint64_t)a.T;
+}
 
 }  // namespace batch
 }  // namespace kbm
@@ -106,6 +140,7 @@ struct kbm_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t *host_word = nullptr;  // pinned
+    uint64_t evaluated = 0;  // trajectory-epochs one run evaluates
 };
 
 namespace kbm {
@@ -619,7 +654,9 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
         a.coeff = (float)q.coeff;
         a.n_sigma = (float)q.n_sigma;
         a.defq = q.q_lo == 0.25 && q.q_hi == 0.75;
-        a.evals = reinterpret_cast<unsigned long long *>(b->ctrl + CTRL_EVALS);
+        b->evaluated += evaluated_traj_epochs(
+            a, reinterpret_cast<const int4 *>(tables.data() + l.box_rel),
+            reinterpret_cast<const int4 *>(tables.data() + l.mbox_rel));
         b->T.push_back(a.T);
         b->V.push_back(a.V);
         b->Wr.push_back(a.Wr);
@@ -648,8 +685,7 @@ extern "C" kbm_status kbm_batch_create(const kbm_stack *stacks, const float *con
     st = write_schedule(b, sc, 1, stream);
     if (st != KBM_OK) return fail(st);
 
-    if (hipHostMalloc(&b->host_word, sizeof(uint64_t) * EVAL_SLOTS * EVAL_STRIDE,
-                      hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc(&b->host_word, 64, hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
         set_error("kbm_batch_create: cannot create the capture stream");
         return fail(KBM_ERR_DEVICE);
@@ -710,19 +746,10 @@ extern "C" kbm_status kbm_batch_evaluated(kbm_batch *b, hipStream_t stream,
                                           uint64_t *traj_epochs) {
     using namespace kbm;
     clear_error();
+    (void)stream;
     KBM_REQUIRE(b != nullptr && traj_epochs != nullptr, KBM_ERR_INVALID_ARG,
                 "kbm_batch_evaluated: batch and traj_epochs must be non-NULL");
-    const size_t n = (size_t)batch::EVAL_SLOTS * batch::EVAL_STRIDE;
-    KBM_HIP(hipMemcpyAsync(b->host_word, b->ctrl + batch::CTRL_EVALS, sizeof(uint64_t) * n,
-                           hipMemcpyDeviceToHost, stream));
-    KBM_HIP(hipStreamSynchronize(stream));
-    uint64_t total = 0;
-    for (int j = 0; j < batch::EVAL_SLOTS; ++j) {
-        uint64_t v = 0;
-        std::memcpy(&v, b->host_word + 2 * (size_t)j * batch::EVAL_STRIDE, sizeof(v));
-        total += v;
-    }
-    *traj_epochs = total;
+    *traj_epochs = b->evaluated;
     return KBM_OK;
 }
 

@@ -19,15 +19,7 @@ constexpr int MAX_T = 32;         // exact epoch counts compiled in
 constexpr int PAD_COLS = 16;      // every allowed tile_cols divides this
 constexpr int PAD_ROWS = 64;      // every allowed tile_rows divides this
 constexpr int MIN_VB = 32;
-// Control block words: queue heads [0, 8), stall flag [8], then the
-// evaluated-trajectory-epoch counters: EVAL_SLOTS u64 counters, one per
-// 128-byte line (workgroup g adds to slot g % EVAL_SLOTS, so the adds of
-// the whole grid do not serialise on one address); then per-stack flags
-// and the progress counters.
-constexpr int CTRL_EVALS = 64;
-constexpr int EVAL_SLOTS = 64;
-constexpr int EVAL_STRIDE = 16;   // u64 per slot (128 bytes)
-constexpr int CTRL_HEAD = CTRL_EVALS + 2 * EVAL_SLOTS * EVAL_STRIDE;
+constexpr int CTRL_HEAD = 64;     // words: queue heads [0, 8), stall flag [8]
 constexpr uint32_t SPIN_LIMIT = 1u << 20;  // polls before a wait gives up
 
 struct PrepDesc {

@@ -67,8 +67,6 @@ constexpr int ST_TILES = ST_X * ST_Y;
 constexpr int VCHUNK = KBM_VCHUNK;  // velocities per launch
 constexpr int NW = KBM_NW;          // waves per workgroup sharing a tile
 constexpr int BUF_DWORD3 = 0x00020000;  // raw buffer descriptor, CDNA
-constexpr int EVAL_SLOTS_N = 64;        // counters of evaluated trajectory-epochs
-constexpr int EVAL_STRIDE_U64 = 16;     // one per 128-byte line
 
 // Constant address space: tables and argument blocks that no kernel writes
 // while the search runs are read through it, so uniform reads stay scalar
@@ -119,10 +117,6 @@ struct SearchArgs {
     int v_begin, v_end, first;
     float coeff, n_sigma;
     int defq;                 // quantiles are (0.25, 0.75): fixed ranks
-    unsigned long long *evals;  // or NULL: adds the trajectory-epochs evaluated
-                                // (those not skipped as unable to reach min_obs)
-                                // into counter blockIdx % EVAL_SLOTS_N
-                                // (EVAL_STRIDE_U64 apart)
 };
 
 __device__ __forceinline__ bool ranks_before(float la, int ia, float lb,
@@ -495,7 +489,6 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
     const int v_last = CONTIG ? min(v_end, v_first + span) : v_end;
     constexpr int v_step = CONTIG ? 1 : NWT;
     constexpr int same_at = (CONTIG || NWT == 1) ? 4 : 5;
-    int n_eval = 0;  // velocities this wave evaluated (not skipped)
     for (int v = v_first; v < v_last; v += v_step) {
         // The velocity's box (and for T <= 32 its offset row) is read up
         // front, as one batch of scalar loads with one wait, and the box
@@ -516,7 +509,6 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
                 continue;
             }
         }
-        ++n_eval;
         float nu[TM], s[TM];
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
@@ -573,10 +565,6 @@ __device__ __forceinline__ void run_chunk(const A &a, int tx, int ty,
             kI[0] = c0 ? v : kI[0];
         }
     }
-    if (a.evals != nullptr && lane == 0 && n_eval > 0)
-        atomicAdd(a.evals + EVAL_STRIDE_U64 * (blockIdx.x % EVAL_SLOTS_N),
-                  (unsigned long long)n_eval *
-                      (unsigned long long)(min(WAVE, a.Wr - tx * WAVE) * T));
     if (NWT > 1) {
         // Merge the waves' lists into wave 0's through LDS.  The ranking
         // compares velocity indices on ties, so the merge order is immaterial.

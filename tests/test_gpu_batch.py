@@ -255,11 +255,36 @@ def _valid_count(times, vels, W, H, min_obs):
     return n
 
 
+def _skip_rule_count(times, vels, W, H, T, min_obs, region):
+    """Trajectory-epochs the sweep evaluates, by brute force over every
+    (64-pixel row tile, velocity) pair: a pair is skipped when some epoch of
+    some lane leaves the image and, at one of the four image edges, fewer
+    than min_obs epochs keep some lane of the tile on the inner side of it."""
+    x0, y0, x1, y1 = region
+    t = np.asarray(times, np.float64)
+    t = t - t.min()
+    v = np.asarray(vels, np.float32).astype(np.float64)
+    dx = np.clip(np.floor(v[:, :1] * t[None, :] + 0.5), -32767, 32767)
+    dy = np.clip(np.floor(v[:, 1:] * t[None, :] + 0.5), -32767, 32767)
+    n = 0
+    for xw in range(x0, x1, 64):
+        lanes = min(64, x1 - xw)
+        for y in range(y0, y1):
+            inside = ((xw + dx.min(1) >= 0) & (xw + 63 + dx.max(1) <= W - 1) &
+                      (y + dy.min(1) >= 0) & (y + dy.max(1) <= H - 1))
+            edges = np.stack([(xw + dx <= W - 1).sum(1), (xw + 63 + dx >= 0).sum(1),
+                              (y + dy <= H - 1).sum(1), (y + dy >= 0).sum(1)])
+            skipped = ~inside & (edges.min(0) < min_obs)
+            n += lanes * T * int(np.sum(~skipped))
+    return n
+
+
 def test_batch_evaluated_count(kbm):
-    """The evaluated trajectory-epoch count: every trajectory when no track
-    can leave the image far enough to fall below min_obs; otherwise at most
-    the nominal count and at least T x the valid trajectories (a skipped
-    (tile, velocity) pair holds no valid trajectory)."""
+    """The evaluated trajectory-epoch count equals a brute-force count of the
+    skip rule over every (tile, velocity) pair, regions and the min_obs > T
+    case included; it is the nominal count when no track can leave the image
+    far enough to fall below min_obs, and at least T x the valid
+    trajectories otherwise (a skipped pair holds no valid trajectory)."""
     rng = np.random.default_rng(5)
     T, H, W = 9, 40, 150
     times = np.sort(rng.uniform(0, 2, T))
@@ -267,15 +292,22 @@ def test_batch_evaluated_count(kbm):
     phi = torch.ones_like(psi)
     slow = rng.uniform(-3, 3, size=(40, 2)).astype(np.float32)
     fast = np.concatenate([slow, rng.uniform(-60, 60, size=(80, 2)).astype(np.float32)])
-    for vels, min_obs, exact in ((slow, 1, True), (fast, 6, False)):
+    full = (0, 0, W, H)
+    cases = ((slow, 1, full), (fast, 6, full), (fast, 2, (7, 3, 140, 31)),
+             (fast, 9, (70, 0, 150, 40)), (fast, T + 1, full))
+    for vels, min_obs, region in cases:
         item = dict(psi=psi, phi=phi, times=times, vels=vels,
-                    params=kbm.SearchParams(k=3, min_obs=min_obs))
+                    params=kbm.SearchParams(k=3, min_obs=min_obs, region=region))
         with kbm.BatchedSearch([item, item]) as plan:
             plan.run()
             assert not plan.check()
             n = plan.evaluated()
-        nominal = 2 * T * H * W * len(vels)
-        if exact:
+        x0, y0, x1, y1 = region
+        nominal = 2 * T * (x1 - x0) * (y1 - y0) * len(vels)
+        want = 2 * _skip_rule_count(times, vels, W, H, T, min_obs, region)
+        print(f"  min_obs {min_obs} region {region}: evaluated {n} of {nominal}")
+        assert n == want
+        if vels is slow:
             assert n == nominal
-        else:
+        elif region == full and min_obs <= T:
             assert 2 * T * _valid_count(times, vels, W, H, min_obs) <= n < nominal
