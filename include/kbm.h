@@ -186,9 +186,11 @@ typedef struct {
                               super-tiles, 4 waves, all that fit, sweep 1 if
                               some stack has >= 16384 velocities else 0 */
 #define KBM_TUNE_AUTO 1    /* time candidate schedules on a probe, keep the
-                              fastest; cached per process and in a file by
-                              library build id, GPU architecture and batch
-                              shape (see kbm_tune_cache_clear) */
+                              fastest if a full run confirms that it beats
+                              the built-in schedule; cached per process and
+                              in a file by library build id, GPU
+                              architecture and batch shape (see
+                              kbm_tune_cache_clear) */
 #define KBM_TUNE_GIVEN 2   /* use *schedule as given */
 
 typedef struct kbm_batch kbm_batch; /* opaque plan with its captured graph */
@@ -203,8 +205,9 @@ kbm_status kbm_batch_workspace_size(const kbm_stack *stacks,
  * the workspace, pick the schedule (tune), and capture the launch sequence
  * (clear control block -> pack planes -> persistent search) into a graph.
  * Synchronous: returns when the workspace is ready.  With KBM_TUNE_AUTO it
- * runs the search several times on a probe (a fraction of every stack's
- * tiles), overwriting `out`.
+ * runs the search several times on a probe (a sixteenth of every stack's
+ * tiles, from the middle of each XCD's share), then the whole batch under
+ * the probe's winner and under the built-in schedule, overwriting `out`.
  *
  *   stacks, p, out, psi, phi : as kbm_search.  The device pointers (psi,
  *       phi, result arrays, workspace) are baked into the graph: they must

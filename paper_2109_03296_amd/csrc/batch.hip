@@ -71,8 +71,8 @@ bool pow2_in(int x, int hi) { return x >= 1 && x <= hi && (x & (x - 1)) == 0; }
 // Built-in schedule: 1024 velocities per item, 4 wavefronts per workgroup
 // sharing a tile, 128 px x 32 row super-tiles, as many workgroups as fit;
 // the waves take contiguous shares of the item's velocities when some stack
-// has at least 16384 velocities, else every fourth velocity.  Measured: the
-// DECam-CCD stack (2048 x 4096, T = 26, 128^2 velocities) takes 1183 ms this
+// has at least 16384 velocities, else every fourth velocity.  Measured when
+// this default was chosen (before the 3-sorter networks): the DECam-CCD stack (2048 x 4096, T = 26, 128^2 velocities) takes 1183 ms this
 // way (interleaved: 1236 ms at its best block, 2048); 62 stacks of 64^2
 // velocities take 10.54 s (contiguous: 10.76 s at its best block, 512).
 Sched default_sched(int vmax) { return Sched{1024, 2, 32, 4, 0, vmax >= 16384 ? 1 : 0}; }
@@ -209,8 +209,10 @@ kbm_status check_sched(const Sched &s) {
 }
 
 // Queue segments and prefix sums for schedule `sc`; with div > 1 each
-// queue keeps only the first ceil(len / div) tiles of every segment (the
-// autotuner's probe).
+// queue keeps only ceil(len / div) consecutive tiles of its share of every
+// stack, taken from the middle of the share (the autotuner's probe: the
+// first tiles are the top rows of the image, where more tracks leave it
+// than in the bulk of the stack).
 kbm_status write_schedule(kbm_batch *b, const Sched &sc, int div, hipStream_t stream) {
     const int S = b->S;
     std::vector<StackInfo> info(S);
@@ -221,7 +223,16 @@ kbm_status write_schedule(kbm_batch *b, const Sched &sc, int div, hipStream_t st
         const uint64_t nt = (uint64_t)nsx * nsy * sc.st_x * sc.st_y;
         KBM_REQUIRE(nt < (1u << 28), KBM_ERR_UNSUPPORTED,
                     "kbm_batch: stack %d has too many tiles", j);
-        info[j] = StackInfo{off, (uint32_t)nt, nsy, 0u};
+        // Every queue's share has floor(nt / 8) or one more tiles; the probe
+        // keeps at most ceil(ceil(nt / 8) / div) of them from probe_off on,
+        // which stays inside the smaller share.
+        uint32_t probe_off = 0;
+        if (div > 1) {
+            const uint64_t lo = nt / NUM_XCD, hi = (nt + NUM_XCD - 1) / NUM_XCD;
+            const uint64_t keep = (hi + div - 1) / div;
+            probe_off = lo > keep ? (uint32_t)((lo - keep) / 2) : 0u;
+        }
+        info[j] = StackInfo{off, (uint32_t)nt, nsy, probe_off};
         off += (uint32_t)nt;
     }
     KBM_REQUIRE(off <= b->max_prog, KBM_ERR_INVALID_ARG,
@@ -326,6 +337,11 @@ kbm_status probe(kbm_batch *b, Sched sc, int div, hipStream_t stream,
     KBM_HIP(hipEventSynchronize(e1));
     KBM_HIP(hipEventElapsedTime(ms, e0, e1));
     return KBM_OK;
+}
+
+bool same_sched(const Sched &x, const Sched &y) {
+    return x.vb == y.vb && x.st_x == y.st_x && x.st_y == y.st_y && x.nw == y.nw &&
+           x.bpc == y.bpc && x.sw == y.sw;
 }
 
 std::mutex g_tune_mutex;
@@ -439,9 +455,12 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
     auto run = [&](const Sched &c, float *t) -> kbm_status {
         return probe(b, c, div, stream, e0, e1, t);
     };
+    const Sched def = cur;
+    float def_ms = 0.0f;
     do {
         if ((st = run(cur, &ms)) != KBM_OK) break;  // warm-up
         if ((st = run(cur, &cur_ms)) != KBM_OK) break;
+        def_ms = cur_ms;
         auto consider = [&](const Sched &c) -> kbm_status {
             float t = 0.0f;
             kbm_status s2 = run(c, &t);
@@ -485,6 +504,18 @@ kbm_status autotune(kbm_batch *b, const kbm_search_params *p, hipStream_t stream
             c.bpc = std::max(1, full * num / 4);
             if (c.bpc >= full) continue;
             if ((st = consider(c)) != KBM_OK) break;
+        }
+        if (st != KBM_OK) break;
+        // The probe ranks schedules on a fraction of the work; its winner
+        // replaces the built-in schedule only if a full run confirms it.
+        if (!same_sched(cur, def)) {
+            float full_def = 0.0f, full_cur = 0.0f;
+            if ((st = probe(b, def, 1, stream, e0, e1, &full_def)) != KBM_OK) break;
+            if ((st = probe(b, cur, 1, stream, e0, e1, &full_cur)) != KBM_OK) break;
+            if (!(full_cur < full_def)) {
+                cur = def;
+                cur_ms = def_ms;
+            }
         }
     } while (false);
     (void)hipEventDestroy(e0);

@@ -34,7 +34,8 @@ struct StackInfo {
     uint32_t prog_off;   // first progress counter of the stack
     uint32_t n_tiles;    // padded tile count (whole super-tiles)
     uint32_t n_super_y;  // super-tiles per column strip
-    uint32_t pad;
+    uint32_t probe_off;  // autotuner probes: first tile of each queue's share
+                         // taken, relative to the share's start (else 0)
 };
 
 // Register budget of the batched kernel: at least this many waves per SIMD
@@ -119,7 +120,8 @@ void batch_kernel(const SearchArgs *__restrict__ descs,
                     const KBM_CONST int *g = (const KBM_CONST int *)seg + 2 * lo;
                     s = g[0];
                     vb = g[1];
-                    t = (int)(cst(info)[s].n_tiles * (uint32_t)q / NUM_XCD + (i - pq[lo]));
+                    t = (int)(cst(info)[s].n_tiles * (uint32_t)q / NUM_XCD +
+                              cst(info)[s].probe_off + (i - pq[lo]));
                     break;
                 }
                 ++hops;
