@@ -17,7 +17,9 @@ namespace {
 // reads elements j, j + 64, ...), then each lane reads its own row from LDS
 // (row stride T rounded up to odd, so the 64 lanes hit 64 different banks).
 // Reading the rows directly would make every load instruction touch up to
-// 64 different cache lines.
+// 64 different cache lines.  All of a lane's loads are issued before the
+// first LDS write, so the block's memory latency is paid once, not once per
+// element.
 constexpr int SG_LANES = 64;
 
 template <int TM>
@@ -25,7 +27,7 @@ __global__ __launch_bounds__(SG_LANES) void sigmag_kernel(
     const float *__restrict__ psi, const float *__restrict__ phi,
     const uint8_t *__restrict__ valid, int64_t n, int T, int quantity, RankTable rt,
     float coeff, float n_sigma, float lh_min, uint64_t *__restrict__ keep,
-    float *__restrict__ lh, uint8_t *__restrict__ pass) {
+    float *__restrict__ lh, uint8_t *__restrict__ pass, int vec) {
     constexpr int RS = TM | 1;  // LDS row stride (odd)
     __shared__ float s_ps[SG_LANES * RS];
     __shared__ float s_ph[SG_LANES * RS];
@@ -33,15 +35,141 @@ __global__ __launch_bounds__(SG_LANES) void sigmag_kernel(
     const int64_t c0 = (int64_t)blockIdx.x * SG_LANES;
     const int rows = (int)min((int64_t)SG_LANES, n - c0);
     const int64_t base = c0 * T;
-    const int count = rows * T;
-    for (int j = threadIdx.x; j < count; j += SG_LANES) {
-        const int r = j / T, i = j - r * T;
-        s_ps[r * RS + i] = psi[base + j];
-        s_ph[r * RS + i] = phi ? phi[base + j] : 1.0f;
-        s_ok[r * RS + i] = valid ? valid[base + j] : (uint8_t)1;
+    const int count = rows * T;  // <= SG_LANES * TM
+    const int lane = threadIdx.x;
+    if (vec) {
+        // 16-byte loads: each workgroup's block starts 16-byte aligned (64 T
+        // floats and 64 T flag bytes from 16-byte aligned arrays).  Lane
+        // k * 64 + lane takes floats 4 q .. 4 q + 3 and flags 16 q .. 16 q + 15
+        // of the block, q its index; the last count % 4 floats and
+        // count % 16 flags are read one by one.
+        constexpr int NF = TM / 4;
+        constexpr int NB = TM >= 16 ? TM / 16 : 1;
+        const int n4 = count >> 2, n16 = count >> 4;
+        const float4 *p4 = reinterpret_cast<const float4 *>(psi + base);
+        const float4 *f4 = phi ? reinterpret_cast<const float4 *>(phi + base) : nullptr;
+        const uint4 *v16 = valid ? reinterpret_cast<const uint4 *>(valid + base) : nullptr;
+        float4 va[NF], vb[NF];
+        uint4 vc[NB];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            const int q = k * SG_LANES + lane;
+            va[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            vb[k] = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+            if (q < n4) {
+                va[k] = p4[q];
+                if (f4) vb[k] = f4[q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int q = k * SG_LANES + lane;
+            vc[k] = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+            if (v16 && q < n16) vc[k] = v16[q];
+        }
+        const int tf = 4 * n4 + lane, tb = 16 * n16 + lane;
+        float xa = 0.0f, xb = 1.0f;
+        uint32_t xc = 1u;
+        if (tf < count) {
+            xa = psi[base + tf];
+            if (phi) xb = phi[base + tf];
+        }
+        if (tb < count && valid) xc = valid[base + tb];
+        // Scatter into the padded rows; (r, i) is stepped without division.
+        int r = (4 * lane) / T, i = 4 * lane - r * T;
+        int dr = (4 * SG_LANES) / T, di = 4 * SG_LANES - dr * T;
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            if (k * SG_LANES + lane < n4) {
+                const float a4[4] = {va[k].x, va[k].y, va[k].z, va[k].w};
+                const float b4[4] = {vb[k].x, vb[k].y, vb[k].z, vb[k].w};
+                int rr = r, ii = i;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    s_ps[rr * RS + ii] = a4[e];
+                    s_ph[rr * RS + ii] = b4[e];
+                    if (++ii == T) {
+                        ii = 0;
+                        ++rr;
+                    }
+                }
+            }
+            r += dr;
+            i += di;
+            if (i >= T) {
+                i -= T;
+                ++r;
+            }
+        }
+        r = (16 * lane) / T;
+        i = 16 * lane - r * T;
+        dr = (16 * SG_LANES) / T;
+        di = 16 * SG_LANES - dr * T;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (k * SG_LANES + lane < n16) {
+                const uint32_t w4[4] = {vc[k].x, vc[k].y, vc[k].z, vc[k].w};
+                int rr = r, ii = i;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    s_ok[rr * RS + ii] = (uint8_t)(w4[e / 4] >> (8 * (e % 4)));
+                    if (++ii == T) {
+                        ii = 0;
+                        ++rr;
+                    }
+                }
+            }
+            r += dr;
+            i += di;
+            while (i >= T) {
+                i -= T;
+                ++r;
+            }
+        }
+        if (tf < count) {
+            const int rt = tf / T;
+            s_ps[rt * RS + (tf - rt * T)] = xa;
+            s_ph[rt * RS + (tf - rt * T)] = xb;
+        }
+        if (tb < count) {
+            const int rt = tb / T;
+            s_ok[rt * RS + (tb - rt * T)] = (uint8_t)xc;
+        }
+    } else {
+        float ga[TM], gb[TM];
+        uint32_t gc[TM];
+#pragma unroll
+        for (int k = 0; k < TM; ++k) {
+            const int j = k * SG_LANES + lane;
+            ga[k] = 0.0f;
+            gb[k] = 1.0f;
+            gc[k] = 1u;
+            if (j < count) {
+                ga[k] = psi[base + j];
+                if (phi) gb[k] = phi[base + j];
+                if (valid) gc[k] = valid[base + j];
+            }
+        }
+        // Row and column of element k * SG_LANES + lane, stepped without division.
+        int r = lane / T, i = lane - r * T;
+        const int dr = SG_LANES / T, di = SG_LANES - dr * T;
+#pragma unroll
+        for (int k = 0; k < TM; ++k) {
+            if (k * SG_LANES + lane < count) {
+                s_ps[r * RS + i] = ga[k];
+                s_ph[r * RS + i] = gb[k];
+                s_ok[r * RS + i] = (uint8_t)gc[k];
+            }
+            r += dr;
+            i += di;
+            if (i >= T) {
+                i -= T;
+                ++r;
+            }
+        }
     }
     __syncthreads();
-    const int l = threadIdx.x;
+    const int l = lane;
     if (l >= rows) return;
     const int64_t c = c0 + l;
     float ps[TM], ph[TM], nu[TM];
@@ -95,9 +223,10 @@ void launch(const float *psi, const float *phi, const uint8_t *valid,
             int64_t n, int T, int quantity, const RankTable &rt, float coeff, float ns,
             float lh_min, uint64_t *keep, float *lh, uint8_t *pass, hipStream_t stream) {
     const int64_t blocks = (n + SG_LANES - 1) / SG_LANES;
+    const int vec = (((uintptr_t)psi | (uintptr_t)phi | (uintptr_t)valid) & 15u) == 0;
     hipLaunchKernelGGL((sigmag_kernel<TM>), dim3((unsigned)blocks), dim3(SG_LANES),
                        0, stream, psi, phi, valid, n, T, quantity, rt, coeff, ns, lh_min,
-                       keep, lh, pass);
+                       keep, lh, pass, vec);
 }
 
 }  // namespace

@@ -294,6 +294,31 @@ def test_sigmag_filter(kbm, oracle_mod, T):
              f"the FP64 decision, all within the binary32 bound")
 
 
+@pytest.mark.parametrize("T", [3, 26, 33])
+def test_sigmag_filter_unaligned_inputs(kbm, T):
+    """Arrays that do not start on a 16-byte boundary take the element-wise
+    staging path; its results equal the 16-byte path's bit for bit, for
+    ragged counts and partial last workgroups."""
+    rng = np.random.default_rng(7 + T)
+    for n in (1, 63, 65, 1000):
+        ps = rng.standard_t(3, size=(n, T)).astype(np.float32)
+        ph = rng.uniform(0.1, 3.0, size=(n, T)).astype(np.float32)
+        valid = (rng.random((n, T)) > 0.15).astype(np.uint8)
+        k_a, l_a = kbm.sigmag_filter(_cuda(ps), _cuda(ph), _cuda(valid))
+        # views one element into larger buffers: 4-byte and 1-byte offsets
+        fb = torch.zeros(n * T + 1, dtype=torch.float32, device="cuda")
+        gb = torch.zeros(n * T + 1, dtype=torch.float32, device="cuda")
+        vb = torch.zeros(n * T + 1, dtype=torch.uint8, device="cuda")
+        fb[1:] = _cuda(ps).reshape(-1)
+        gb[1:] = _cuda(ph).reshape(-1)
+        vb[1:] = _cuda(valid).reshape(-1)
+        psv, phv, vv = fb[1:].view(n, T), gb[1:].view(n, T), vb[1:].view(n, T)
+        assert psv.data_ptr() % 16 != 0 and vv.data_ptr() % 16 != 0
+        k_u, l_u = kbm.sigmag_filter(psv, phv, vv)
+        assert torch.equal(k_u, k_a)
+        assert torch.equal(l_u.view(torch.int32), l_a.view(torch.int32))
+
+
 # ---------------------------------------------------------------- refine --
 def _refine_setup(oracle_mod, n=2000, seed=5):
     st = synth.make_config(2, size=(256, 192), n_vel=(4, 4))
