@@ -39,10 +39,10 @@ __global__ __launch_bounds__(SG_LANES) void sigmag_kernel(
     const int lane = threadIdx.x;
     if (vec) {
         // 16-byte loads: each workgroup's block starts 16-byte aligned (64 T
-        // floats and 64 T flag bytes from 16-byte aligned arrays).  Lane
-        // k * 64 + lane takes floats 4 q .. 4 q + 3 and flags 16 q .. 16 q + 15
-        // of the block, q its index; the last count % 4 floats and
-        // count % 16 flags are read one by one.
+        // floats and 64 T flag bytes from 16-byte aligned arrays).  For
+        // k = 0, 1, ... the lane takes the q-th float4 (floats 4q .. 4q+3) and
+        // the q-th 16-byte group of flags of the block, q = k * 64 + lane;
+        // the last count % 4 floats and count % 16 flags are read one by one.
         constexpr int NF = TM / 4;
         constexpr int NB = TM >= 16 ? TM / 16 : 1;
         const int n4 = count >> 2, n16 = count >> 4;
