@@ -347,7 +347,7 @@ extern "C" kbm_status kbm_make_planes(const kbm_stack *s, const float *sci,
             KBM_SEP_CASE(25) KBM_SEP_CASE(27) KBM_SEP_CASE(29) KBM_SEP_CASE(31)
 #undef KBM_SEP_CASE
         }
-        KBM_LAUNCHED("planes_sep_kernel");
+        KBM_LAUNCHED("planes_stream_kernel");
         return KBM_OK;
     }
     const int rows = PSF_ARG_MAX / psf_k;  // >= 20 for psf_k <= 31
