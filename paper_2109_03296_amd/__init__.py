@@ -374,7 +374,8 @@ class BatchedSearch:
     launch per run, replayed from a HIP graph captured at construction.
 
     ``items`` as for search_batched.  ``tune``: TUNE_DEFAULT, TUNE_AUTO
-    (time candidate schedules on a probe and keep the fastest), or a
+    (time candidate schedules on a probe and keep the fastest if a full run
+    confirms that it beats the built-in schedule), or a
     Schedule / dict of its fields (used as given).  The plane tensors,
     results and workspace are held by this object: refill ``psi``/``phi`` in
     place and call run() again to search new images of the same geometry.
