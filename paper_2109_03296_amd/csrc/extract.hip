@@ -7,7 +7,10 @@
 // its likelihood in the high word and the complement of its flat slot index
 // in the low word, so keys are unique and "larger key" means "higher L',
 // then smaller index".  An 8-pass radix select (8 bits per pass, histograms
-// in LDS then global atomics) finds the N-th largest key; an ordered
+// in LDS then global atomics) finds the N-th largest key (it stops early
+// once the bucket of the N-th key is taken whole: then every key at or above
+// the prefix found so far is selected, which with distinct likelihoods
+// happens after the four passes over the likelihood bits); an ordered
 // compaction (block counts, one scan, block-local ballot ranks) then writes
 // the selected slots in flat-index order.  Slots below the threshold, empty
 // or non-finite never take part.
@@ -28,6 +31,7 @@ struct ExtractState {
     unsigned long long remain;  // how many keys still to take at this prefix
     unsigned long long total;   // eligible slots
     unsigned int none;          // nothing to select (no eligible slot, or N = 0)
+    unsigned int done;          // prefix is final: the remaining passes do nothing
     unsigned int hist[256];
 };
 
@@ -51,6 +55,7 @@ __global__ __launch_bounds__(256) void ex_init_kernel(ExtractState *st, uint64_t
         st->remain = n_max;
         st->total = 0;
         st->none = 0;
+        st->done = 0;
     }
     st->hist[threadIdx.x] = 0;
 }
@@ -60,6 +65,7 @@ __global__ __launch_bounds__(256) void ex_init_kernel(ExtractState *st, uint64_t
 __global__ __launch_bounds__(EX_THREADS) void ex_hist_kernel(
     const float *__restrict__ lh, uint64_t n, float lh_min, int pass,
     ExtractState *st) {
+    if (st->done) return;
     __shared__ unsigned int h[256];
     __shared__ unsigned long long cnt;
     h[threadIdx.x] = 0;
@@ -85,8 +91,13 @@ __global__ __launch_bounds__(EX_THREADS) void ex_hist_kernel(
 }
 
 // Choose the byte of the N-th largest key at this pass (scan from 255 down).
-// After the eighth pass `prefix` is that key; exactly N keys are >= it.
+// After the eighth pass `prefix` is that key; exactly N keys are >= it.  If
+// the chosen bucket holds exactly the keys still needed, all of them are
+// taken: `prefix` with its lower bytes zero is then already a threshold with
+// exactly N keys >= it, and the remaining passes are skipped.
 __global__ __launch_bounds__(256) void ex_pick_kernel(ExtractState *st, int pass) {
+    if (st->done) return;
+    __syncthreads();  // every thread has read `done` before thread 0 may set it
     if (threadIdx.x == 0) {
         if (pass == 0) {
             if (st->total < st->remain) st->remain = st->total;
@@ -102,6 +113,7 @@ __global__ __launch_bounds__(256) void ex_pick_kernel(ExtractState *st, int pass
                 need -= c;
             }
             st->prefix |= (unsigned long long)b << shift;
+            st->done = st->hist[b] == need;
             st->remain = need;
         }
     }

@@ -58,6 +58,25 @@ def test_extract_top_exact(kbm, oracle_mod, n_max, lh_min):
         np.testing.assert_array_equal(out["keep"].cpu().numpy(), keep.ravel()[want])
 
 
+@pytest.mark.parametrize("n_max", [1, 2, 37, 4096, 10 ** 6])
+def test_extract_top_distinct_likelihoods(kbm, oracle_mod, n_max):
+    """Distinct likelihoods: the radix select usually finishes once the
+    likelihood bits are resolved (the N-th key's bucket is taken whole);
+    the selection still equals the oracle's, slot for slot."""
+    Hr, Wr, K, V = 64, 96, 4, 9
+    res, lh, vidx, *_ , vels = _fake_results(11, Hr, Wr, K, V)
+    rng = np.random.default_rng(12)
+    fin = np.isfinite(lh)
+    vals = rng.permutation(int(fin.sum())).astype(np.float32) * np.float32(0.001) - 5.0
+    lh[fin] = vals                                   # distinct, all exact in binary32
+    res["lh"] = torch.from_numpy(lh).cuda()
+    out = kbm.extract_top(res, vels, n_max, -np.inf)
+    torch.cuda.synchronize()
+    want = oracle_mod.extract_top(lh, n_max, -np.inf)
+    np.testing.assert_array_equal(out["index"].cpu().numpy(), want)
+    np.testing.assert_array_equal(out["lh"].cpu().numpy(), lh.ravel()[want])
+
+
 def test_adam_step_matches_oracle(kbm, oracle_mod):
     rng = np.random.default_rng(3)
     n = 1000
