@@ -112,6 +112,31 @@ def test_batch_matches_per_stack_search(kbm, batch):
             _equal(r, b["plain"])
 
 
+def test_batch_other_percentiles(kbm):
+    """Stacks with other percentile pairs, clipping widths and masked samples
+    (the runtime-rank path of the fused filter) give the per-stack search's
+    results bit for bit in one persistent launch."""
+    _say("batch: other percentile pairs")
+    items = []
+    for seed, (T, ql, qh, c, ns) in enumerate([(26, 0.16, 0.84, 0.5035, 2.0),
+                                              (17, 0.10, 0.90, 0.39, 3.0),
+                                              (9, 0.25, 0.75, 0.7413, 1.5)]):
+        st = synth.tiny_stack(40 + seed, W=130, H=37, T=T, n_vel=40, max_speed=12.0,
+                              mask_rate=0.1)
+        psi, phi = kbm.make_planes(torch.from_numpy(st.sci).cuda(),
+                                   torch.from_numpy(st.var).cuda(),
+                                   torch.from_numpy(st.mask).cuda(), st.psf)
+        items.append(dict(psi=psi, phi=phi, times=st.times, vels=st.vels,
+                          params=kbm.SearchParams(k=4, min_obs=max(1, T // 2), q_lo=ql,
+                                                  q_hi=qh, coeff=c, n_sigma=ns)))
+    with kbm.BatchedSearch(items) as plan:
+        plan.run()
+        assert not plan.check(), "dependency wait gave up"
+        for it, r in zip(items, plan.results):
+            ref = kbm.search(it["psi"], it["phi"], it["times"], it["vels"], it["params"])
+            _equal(r, ref)
+
+
 def test_batch_protocol_B(kbm, oracle_mod, batch):
     _say("batch: protocol B against the oracle")
     res, _ = _run(kbm, batch, kbm.TUNE_DEFAULT)

@@ -164,6 +164,13 @@ SEARCH_CASES = {
                                           mask_rate=0.3), dict(k=4, min_obs=10), None),
     "tiny_t64": (lambda: synth.tiny_stack(14, W=20, H=18, T=64, n_vel=7),
                  dict(k=2, min_obs=1, n_sigma=1.0), None),
+    # other percentile pairs take the runtime-rank path of the fused filter
+    "c2crop_q16_84": (lambda: synth.make_config(2, size=(300, 200), n_vel=(12, 16)),
+                      dict(q_lo=0.16, q_hi=0.84, coeff=0.5035), None),
+    "tiny_t17_q10_90": (lambda: synth.tiny_stack(17, W=33, H=21, T=17, n_vel=19,
+                                                 max_speed=9.0, mask_rate=0.1),
+                        dict(k=3, min_obs=5, q_lo=0.1, q_hi=0.9, coeff=0.39,
+                             n_sigma=3.0), None),
 }
 
 
