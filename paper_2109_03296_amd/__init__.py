@@ -855,6 +855,10 @@ def refine(psi, phi, times, params0, keep=None, steps=50, lr_pos=0.3,
     likelihood at the returned params."""
     if mode not in ("fused", "graph", "eager"):
         raise ValueError(f"mode must be fused, graph or eager, not {mode!r}")
+    if params0.shape[0] == 0:  # nothing to launch (and no graph to capture)
+        _dev(params0, torch.float32, "params0")
+        return (params0.detach().clone(),
+                torch.empty(0, dtype=torch.float32, device=params0.device))
     if mode == "fused" and steps <= REFINE_MAX_FUSED_STEPS:
         p = params0.detach().clone().contiguous()
         lh = refine_adam(psi, phi, times, p,

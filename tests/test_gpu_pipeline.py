@@ -338,3 +338,26 @@ def test_results_per_pixel_inline_filter_keeps_sources(kbm):
           f"in-line {len(found[True])} of {len(st.sources)}", flush=True)
     assert len(found[True]) > len(found[False])
     assert len(found[True]) >= 0.75 * len(st.sources)
+
+
+def test_empty_candidate_lists(kbm):
+    """Zero candidates or lightcurves: every candidate-level call returns
+    empty results without error."""
+    st = synth.tiny_stack(21, W=40, H=30, T=6, n_vel=4)
+    sci, var, mask = (torch.from_numpy(a).cuda() for a in (st.sci, st.var, st.mask))
+    psi, phi = kbm.make_planes(sci, var, mask, st.psf)
+    none4 = torch.zeros((0, 4), dtype=torch.float32, device="cuda")
+    assert kbm.refine_forward(psi, phi, st.times, none4).numel() == 0
+    for mode in ("fused", "graph", "eager"):
+        p, lh = kbm.refine(psi, phi, st.times, none4.clone(), steps=5, mode=mode)
+        assert p.shape == (0, 4) and lh.numel() == 0
+    sc = kbm.score_trajectories(psi, phi, st.times, none4, kbm.SearchParams(k=1))
+    assert sc["lh"].numel() == 0
+    sp = kbm.stamps(sci, var, mask, st.times, none4, radius=3)
+    assert sp["passed"].numel() == 0 and sp["moments"].shape[0] == 0
+    curves = torch.zeros((0, 6), dtype=torch.float32, device="cuda")
+    keep, lhf = kbm.sigmag_filter(curves, curves)
+    assert keep.numel() == 0 and lhf.numel() == 0
+    k2, l2, ok = kbm.sigmag_filter_ex(curves, curves, lh_min=10.0)
+    assert k2.numel() == 0 and ok.numel() == 0
+    torch.cuda.synchronize()
